@@ -1,0 +1,215 @@
+/*
+ * dpso.h - C ABI of the MI355X (gfx950) library for the enhanced discrete
+ * particle swarm optimisation of UAV inspection paths (Phung, Quach, Dinh, Ha,
+ * "Enhanced Discrete Particle Swarm Optimization Path Planning for UAV
+ * Vision-based Surface Inspection", arXiv 1706.04399).
+ *
+ * The inspection path is a travelling-salesman tour over camera viewpoints
+ * with obstacle-aware travelling costs (Sect. 2.3). A swarm of particles,
+ * each a tour, evolves by the discrete velocity update of Sect. 3.1, random
+ * mutation (Sect. 3.2.2) and complete 2-opt edge exchange (Sect. 3.2.3),
+ * following the pseudo code of Sect. 3.3.
+ *
+ * Conventions
+ *  - Labels are 0..n-1 (the paper's nodes 1..N). A tour is n labels; the
+ *    return to the first node is implicit.
+ *  - Distances are int32 millimetres, row-major [n][n], symmetric, zero on
+ *    the diagonal, 0 <= d < DPSO_D_INF, or DPSO_D_INF for a pair with no
+ *    obstacle-free path (the paper's "very large cost", Sect. 2.3). Costs are
+ *    int64.
+ *  - Pointers prefixed d_ are device memory on the current HIP device; h_
+ *    pointers and dpso_scene arrays are host memory. The caller owns every
+ *    buffer and keeps it alive until the work enqueued on `stream` is done.
+ *    `stream` is a hipStream_t (NULL = the null stream).
+ *  - Calls that only enqueue work return before it finishes; a device fault
+ *    surfaces as DPSO_E_DEVICE at a later call. Calls documented as
+ *    synchronising wait for `stream`.
+ *  - Errors are returned, never thrown. dpso_last_error() gives a
+ *    thread-local text for the last failing call of the calling thread.
+ *  - Arguments are validated before any device work is enqueued, so a
+ *    rejected call has no effect.
+ */
+#ifndef DPSO_H
+#define DPSO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t dpso_status;
+#define DPSO_OK 0
+#define DPSO_E_INVAL (-1)  /* null pointer, bad size or parameter              */
+#define DPSO_E_RANGE (-2)  /* value outside what the library supports          */
+#define DPSO_E_NOMEM (-3)  /* a caller buffer is smaller than required         */
+#define DPSO_E_DEVICE (-4) /* a HIP call failed (text in dpso_last_error)       */
+#define DPSO_E_STATE (-5)  /* state buffer not initialised for this n / swarm  */
+
+#define DPSO_D_INF 268435455 /* 2^28 - 1 */
+#define DPSO_MAX_N 4096      /* largest number of viewpoints                    */
+#define DPSO_MAX_SWARM 65536 /* largest swarm                                   */
+#define DPSO_MAX_GRAPH 16384 /* largest n + 8 * n_boxes (visibility-graph nodes)  */
+
+/* Edge-exchange trigger (pseudo code of Sect. 3.3: exchange when the global
+ * best did not improve; ALWAYS runs it every generation). */
+#define DPSO_EE_OFF 0
+#define DPSO_EE_ON_STALL 1
+#define DPSO_EE_ALWAYS 2
+
+/* A scene (Sect. 2.1-2.2): viewpoint positions and axis-aligned box
+ * obstacles in integer mm; boxes are inflated by clearance_mm (the UAV's
+ * size). Coordinates must satisfy |c| < 2^26 after inflation, and
+ * n + 8 * n_boxes <= DPSO_MAX_GRAPH. */
+typedef struct {
+    const int32_t *vp_mm;    /* host [n][3]: x, y, z                        */
+    int32_t n;               /* 1 <= n <= DPSO_MAX_N                         */
+    const int32_t *boxes_mm; /* host [n_boxes][6]: lo x, y, z, hi x, y, z   */
+    int32_t n_boxes;         /* >= 0                                         */
+    int32_t clearance_mm;    /* >= 0                                         */
+} dpso_scene;
+
+/* Swarm parameters (pseudo code of Sect. 3.3). Coefficients of eq. velocity
+ * are Q16 fixed point: value * 65536, at most 2.0 (131072). A coefficient
+ * product above one keeps the whole transposition list. */
+typedef struct {
+    int32_t swarm_size;      /* 1..DPSO_MAX_SWARM                                   */
+    int32_t max_generations; /* generations after initialisation (>= 0)             */
+    uint32_t w_q16;          /* inertia w                                           */
+    uint32_t phi1_q16;       /* cognitive coefficient phi1                          */
+    uint32_t phi2_q16;       /* social coefficient phi2                             */
+    int32_t mutation_period; /* mutate on generations t % period == 0; 0 = never    */
+    int32_t ee_trigger;      /* DPSO_EE_*                                           */
+    int32_t ee_max_moves;    /* exchanges per particle per invocation; 0 = until no
+                                improving exchange remains                          */
+    int32_t stall_limit;     /* stop after this many generations without a better
+                                global best; 0 = never                             */
+    int32_t det_permille;    /* share of nearest-neighbour seeded particles (0..1000) */
+    uint64_t seed;           /* Philox key word 0                                   */
+    uint64_t instance;       /* Philox key word 1                                   */
+} dpso_params;
+
+/* Progress of a swarm, read by dpso_get_info. */
+typedef struct {
+    int32_t n, swarm_size, trace_capacity;
+    int32_t generation;      /* generations completed (0 after init)            */
+    int32_t stall;           /* generations since the global best last improved */
+    int32_t done;            /* max_generations or stall_limit reached          */
+    int64_t best_cost;       /* cost of the global best tour                    */
+    int64_t sweeps;          /* complete 2-opt neighbourhood searches run       */
+    int64_t moves;           /* 2-opt exchanges applied                         */
+    int64_t reshuffled;      /* particles restarted by mutation                 */
+} dpso_info;
+
+/* Host view of a swarm state for dpso_export_state / dpso_import_state.
+ * Arrays are row-major; velocity row p holds vlen[p] transpositions
+ * (label a, label b). */
+typedef struct {
+    uint16_t *X;    /* [S][n] current tours          */
+    uint16_t *P;    /* [S][n] personal-best tours    */
+    uint16_t *V;    /* [S][n][2] velocities          */
+    int32_t *vlen;  /* [S]                           */
+    int64_t *F;     /* [S] cost of X                 */
+    int64_t *FP;    /* [S] cost of P                 */
+    uint16_t *G;    /* [n] global-best tour          */
+    int64_t *trace; /* [trace_capacity] global-best cost after each generation */
+    int32_t generation, stall, done;
+    int64_t best_cost;
+} dpso_host_state;
+
+/* Library version string. */
+const char *dpso_version(void);
+
+/* Text of the last error returned to the calling thread ("" if none). */
+const char *dpso_last_error(void);
+
+/* Checks parameters against n without touching the device. */
+dpso_status dpso_validate_params(const dpso_params *params, int32_t n);
+
+/* Exact size of the device state buffer for n viewpoints, a swarm of
+ * swarm_size and max_generations generations; 0 if the sizes are out of
+ * range. The buffer holds every particle's tour, personal best and
+ * velocity, costs, the global best, the cost trace and the scratch space
+ * used by the generation loop: dpso_run allocates nothing. */
+size_t dpso_state_bytes(int32_t n, int32_t swarm_size, int32_t max_generations);
+
+/* Bytes of device workspace dpso_build_dist needs for this scene size. */
+size_t dpso_dist_work_bytes(int32_t n, int32_t n_boxes);
+
+/* Travelling costs between all viewpoints (Sect. 2.2-2.3): the cost of the
+ * shortest path in the visibility graph whose nodes are the viewpoints and
+ * the corners of the inflated boxes. A straight flight is allowed iff it
+ * misses the open interior of every inflated box; it costs its Euclidean
+ * length rounded half up to whole mm. Writes d_dist (device int32 [n][n]).
+ * d_work (device, dpso_dist_work_bytes) is scratch. Synchronises `stream`.
+ * Returns DPSO_E_RANGE if a finite path cost reaches DPSO_D_INF. */
+dpso_status dpso_build_dist(const dpso_scene *scene, int32_t *d_dist, void *d_work,
+                            size_t work_bytes, void *stream);
+
+/* Initial swarm (pseudo code of Sect. 3.3, deterministic initialisation of
+ * Sect. 3.2.1): the first ceil(S * det_permille / 1000) particles start from
+ * nearest-neighbour tours whose start labels are spread evenly over 0..n-1
+ * (smallest label on ties); the others from Philox Fisher-Yates shuffles.
+ * Velocities are empty, personal bests are the particles themselves and the
+ * global best is the cheapest (lowest index on ties). d_state must hold
+ * dpso_state_bytes(n, S, max_generations) bytes. Enqueues only. */
+dpso_status dpso_init_nn(const int32_t *d_dist, int32_t n, const dpso_params *params,
+                         void *d_state, size_t state_bytes, void *stream);
+
+/* Runs up to `generations` more generations (eq. velocity, eq. position,
+ * mutation, global-best update, edge exchange), stopping early once
+ * max_generations or stall_limit is reached; resumes from the generation
+ * the state holds, so run(a) followed by run(b) equals run(a + b). params
+ * must be those given to dpso_init_nn. Enqueues only; a state that was not
+ * initialised for (n, swarm_size) is reported as DPSO_E_STATE by the next
+ * dpso_get_info / dpso_get_best. */
+dpso_status dpso_run(const int32_t *d_dist, int32_t n, const dpso_params *params, void *d_state,
+                     size_t state_bytes, int32_t generations, void *stream);
+
+/* Device time of each phase of the generation loop, summed over a
+ * dpso_run_profiled call (HIP events recorded on `stream` between phases). */
+typedef struct {
+    float ms_total;     /* first to last event                                 */
+    float ms_move;      /* velocity / position update, cost, personal best     */
+    float ms_mutation;  /* duplicate marking, ranking and reshuffles           */
+    float ms_gbest;     /* both global-best reductions                         */
+    float ms_exchange;  /* 2-opt edge exchange                                 */
+    float ms_control;   /* end-of-generation step                              */
+    int32_t generations;        /* generations enqueued                        */
+    int32_t exchange_launches;  /* edge-exchange kernel launches               */
+} dpso_phase_times;
+
+/* dpso_run with a HIP event between the phases of every generation; fills
+ * *times and synchronises `stream`. Results are identical to dpso_run. */
+dpso_status dpso_run_profiled(const int32_t *d_dist, int32_t n, const dpso_params *params,
+                              void *d_state, size_t state_bytes, int32_t generations,
+                              dpso_phase_times *times, void *stream);
+
+/* Progress counters. Synchronises `stream`. */
+dpso_status dpso_get_info(const void *d_state, dpso_info *info, void *stream);
+
+/* Global best: h_tour (host [n]) receives the tour as stored, *h_cost its
+ * cost, *h_generation the generations completed; h_trace (nullable, host
+ * [generation + 1]) the global-best cost after each generation. Any output
+ * pointer may be NULL. Synchronises `stream`. */
+dpso_status dpso_get_best(const void *d_state, int32_t *h_tour, int64_t *h_cost,
+                          int32_t *h_generation, int64_t *h_trace, void *stream);
+
+/* Copies the whole swarm to host arrays (checkpoint, inspection). n and
+ * swarm_size must match the state. Synchronises `stream`. */
+dpso_status dpso_export_state(const void *d_state, int32_t n, int32_t swarm_size,
+                              dpso_host_state *out, void *stream);
+
+/* Replaces the swarm with host arrays (resume from a checkpoint). The state
+ * must have been initialised for (n, swarm_size); trace entries
+ * 0..generation are copied. Tours must be permutations of 0..n-1 and
+ * vlen[p] <= n - 1 (checked on the host). Synchronises `stream`. */
+dpso_status dpso_import_state(void *d_state, size_t state_bytes, int32_t n, int32_t swarm_size,
+                              const dpso_host_state *in, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DPSO_H */

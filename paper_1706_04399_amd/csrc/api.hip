@@ -1,0 +1,396 @@
+// C ABI entry points: argument validation, state layout and launch order.
+// See include/dpso.h for the contract of each call.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <mutex>
+#include <vector>
+
+#include "dpso.h"
+#include "kernels.hpp"
+
+namespace {
+
+thread_local char g_error[512] = "";
+
+dpso_status fail(dpso_status code, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_error, sizeof g_error, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+dpso_status ok()
+{
+    g_error[0] = 0;
+    return DPSO_OK;
+}
+
+dpso_status hip_fail(hipError_t e, const char *what)
+{
+    return fail(DPSO_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, what)                              \
+    do {                                                 \
+        hipError_t e_ = (expr);                          \
+        if (e_ != hipSuccess) return hip_fail(e_, what); \
+    } while (0)
+
+dpso_status check_params(const dpso_params *p, int32_t n)
+{
+    if (!p) return fail(DPSO_E_INVAL, "params is NULL");
+    if (n < 1) return fail(DPSO_E_INVAL, "n = %d must be at least 1", n);
+    if (n > DPSO_MAX_N) return fail(DPSO_E_RANGE, "n = %d exceeds DPSO_MAX_N = %d", n, DPSO_MAX_N);
+    if (p->swarm_size < 1 || p->swarm_size > DPSO_MAX_SWARM)
+        return fail(DPSO_E_INVAL, "swarm_size = %d outside 1..%d", p->swarm_size, DPSO_MAX_SWARM);
+    if (p->max_generations < 0 || p->max_generations > (1 << 30))
+        return fail(DPSO_E_INVAL, "max_generations = %d outside 0..2^30", p->max_generations);
+    if (p->w_q16 > 131072 || p->phi1_q16 > 131072 || p->phi2_q16 > 131072)
+        return fail(DPSO_E_INVAL, "coefficients must be at most 2.0 (131072 in Q16)");
+    if (p->mutation_period < 0) return fail(DPSO_E_INVAL, "mutation_period must be >= 0");
+    if (p->ee_trigger < DPSO_EE_OFF || p->ee_trigger > DPSO_EE_ALWAYS)
+        return fail(DPSO_E_INVAL, "ee_trigger = %d is not a DPSO_EE_* value", p->ee_trigger);
+    if (p->ee_max_moves < 0) return fail(DPSO_E_INVAL, "ee_max_moves must be >= 0");
+    if (p->stall_limit < 0) return fail(DPSO_E_INVAL, "stall_limit must be >= 0");
+    if (p->det_permille < 0 || p->det_permille > 1000)
+        return fail(DPSO_E_INVAL, "det_permille = %d outside 0..1000", p->det_permille);
+    return DPSO_OK;
+}
+
+dpso::KParams kernel_params(const dpso_params *p)
+{
+    dpso::KParams k{};
+    k.seed = p->seed;
+    k.instance = p->instance;
+    k.w_q16 = p->w_q16;
+    k.phi1_q16 = p->phi1_q16;
+    k.phi2_q16 = p->phi2_q16;
+    k.mutation_period = p->mutation_period;
+    k.ee_trigger = p->ee_trigger;
+    k.ee_max_moves = p->ee_max_moves;
+    k.stall_limit = p->stall_limit;
+    k.max_generations = p->max_generations;
+    int64_t m = (int64_t(p->swarm_size) * p->det_permille + 999) / 1000;
+    k.det_count = int32_t(m < p->swarm_size ? m : p->swarm_size);
+    return k;
+}
+
+hipStream_t as_stream(void *s) { return static_cast<hipStream_t>(s); }
+
+// Reads the header of a state (synchronising the stream).
+dpso_status read_header(const void *d_state, dpso::Hdr *h, hipStream_t s)
+{
+    if (!d_state) return fail(DPSO_E_INVAL, "state is NULL");
+    HIP_TRY(hipMemcpyAsync(h, d_state, sizeof *h, hipMemcpyDeviceToHost, s), "read state header");
+    HIP_TRY(hipStreamSynchronize(s), "synchronise stream");
+    if (h->magic != dpso::kMagic || h->n < 1 || h->n > DPSO_MAX_N || h->S < 1 ||
+        h->S > DPSO_MAX_SWARM || h->cap < 1)
+        return fail(DPSO_E_STATE, "state buffer is not an initialised swarm");
+    if (h->err) return fail(DPSO_E_STATE, "state rejected by dpso_run: it does not match n / swarm_size");
+    return DPSO_OK;
+}
+
+// Event pool for dpso_run_profiled, reused across calls.
+std::mutex g_event_mutex;
+std::vector<hipEvent_t> g_events;
+
+dpso_status events(size_t count, std::vector<hipEvent_t> &out)
+{
+    std::lock_guard<std::mutex> lock(g_event_mutex);
+    while (g_events.size() < count) {
+        hipEvent_t e;
+        HIP_TRY(hipEventCreate(&e), "create event");
+        g_events.push_back(e);
+    }
+    out.assign(g_events.begin(), g_events.begin() + count);
+    return DPSO_OK;
+}
+
+dpso_status run_impl(const int32_t *d_dist, int32_t n, const dpso_params *params, void *d_state,
+                     size_t state_bytes, int32_t generations, void *stream, dpso_phase_times *times)
+{
+    dpso_status st = check_params(params, n);
+    if (st) return st;
+    if (!d_dist || !d_state) return fail(DPSO_E_INVAL, "d_dist and d_state must be non-NULL");
+    if (generations < 0) return fail(DPSO_E_INVAL, "generations must be >= 0");
+    const dpso::Layout L = dpso::make_layout(n, params->swarm_size, params->max_generations + 1);
+    if (state_bytes < L.total)
+        return fail(DPSO_E_NOMEM, "state buffer of %zu bytes, %zu needed", state_bytes, L.total);
+    const dpso::View v = dpso::make_view(d_state, L);
+    const dpso::KParams kp = kernel_params(params);
+    hipStream_t s = as_stream(stream);
+    std::vector<hipEvent_t> ev;
+    constexpr int kMarks = 6;  // after move, mutation, gbest, exchange, gbest, end
+    if (times && (st = events(size_t(generations) * kMarks + 1, ev))) return st;
+    size_t mark = 0;
+    auto stamp = [&]() -> hipError_t { return times ? hipEventRecord(ev[mark++], s) : hipSuccess; };
+    HIP_TRY(dpso::launch_check(v, L.cap, s), "launch check");
+    HIP_TRY(stamp(), "record event");
+    for (int32_t g = 0; g < generations; ++g) {
+        HIP_TRY(dpso::launch_move(d_dist, v, kp, s), "launch move");
+        HIP_TRY(stamp(), "record event");
+        if (kp.mutation_period > 0) HIP_TRY(dpso::launch_mutation(d_dist, v, kp, s), "launch mutation");
+        HIP_TRY(stamp(), "record event");
+        HIP_TRY(dpso::launch_gbest(v, kp, 1, s), "launch gbest");
+        HIP_TRY(stamp(), "record event");
+        if (kp.ee_trigger != DPSO_EE_OFF) HIP_TRY(dpso::launch_2opt(d_dist, v, kp, s), "launch 2-opt");
+        HIP_TRY(stamp(), "record event");
+        if (kp.ee_trigger != DPSO_EE_OFF) HIP_TRY(dpso::launch_gbest(v, kp, 2, s), "launch gbest");
+        HIP_TRY(stamp(), "record event");
+        HIP_TRY(dpso::launch_end(v, kp, s), "launch end");
+        HIP_TRY(stamp(), "record event");
+    }
+    if (times) {
+        HIP_TRY(hipStreamSynchronize(s), "synchronise stream");
+        dpso_phase_times t{};
+        float *slot[kMarks] = {&t.ms_move, &t.ms_mutation, &t.ms_gbest,
+                               &t.ms_exchange, &t.ms_gbest, &t.ms_control};
+        for (int32_t g = 0; g < generations; ++g)
+            for (int k = 0; k < kMarks; ++k) {
+                float ms = 0.f;
+                const size_t i = size_t(g) * kMarks + k;
+                HIP_TRY(hipEventElapsedTime(&ms, ev[i], ev[i + 1]), "event time");
+                *slot[k] += ms;
+            }
+        if (generations > 0) HIP_TRY(hipEventElapsedTime(&t.ms_total, ev[0], ev[mark - 1]), "event time");
+        t.generations = generations;
+        t.exchange_launches = kp.ee_trigger != DPSO_EE_OFF ? generations : 0;
+        *times = t;
+    }
+    return ok();
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *dpso_version(void) { return "dpso-mi355x 0.1 (gfx950)"; }
+
+const char *dpso_last_error(void) { return g_error; }
+
+dpso_status dpso_validate_params(const dpso_params *params, int32_t n)
+{
+    dpso_status st = check_params(params, n);
+    return st ? st : ok();
+}
+
+size_t dpso_state_bytes(int32_t n, int32_t swarm_size, int32_t max_generations)
+{
+    if (n < 1 || n > DPSO_MAX_N || swarm_size < 1 || swarm_size > DPSO_MAX_SWARM ||
+        max_generations < 0 || max_generations > (1 << 30))
+        return 0;
+    return dpso::make_layout(n, swarm_size, max_generations + 1).total;
+}
+
+size_t dpso_dist_work_bytes(int32_t n, int32_t n_boxes)
+{
+    if (n < 1 || n > DPSO_MAX_N || n_boxes < 0 || int64_t(n) + 8 * int64_t(n_boxes) > DPSO_MAX_GRAPH)
+        return 0;
+    return dpso::dist_work_bytes(n, n_boxes);
+}
+
+dpso_status dpso_build_dist(const dpso_scene *scene, int32_t *d_dist, void *d_work, size_t work_bytes,
+                            void *stream)
+{
+    if (!scene || !d_dist || !d_work) return fail(DPSO_E_INVAL, "scene, d_dist and d_work must be non-NULL");
+    const int32_t n = scene->n, nb = scene->n_boxes;
+    if (n < 1) return fail(DPSO_E_INVAL, "scene has n = %d viewpoints", n);
+    if (n > DPSO_MAX_N) return fail(DPSO_E_RANGE, "n = %d exceeds DPSO_MAX_N", n);
+    if (nb < 0 || (nb > 0 && !scene->boxes_mm) || !scene->vp_mm)
+        return fail(DPSO_E_INVAL, "bad box list (n_boxes = %d)", nb);
+    if (int64_t(n) + 8 * int64_t(nb) > DPSO_MAX_GRAPH)
+        return fail(DPSO_E_RANGE, "n + 8 * n_boxes = %lld exceeds DPSO_MAX_GRAPH = %d",
+                    (long long)(int64_t(n) + 8 * int64_t(nb)), DPSO_MAX_GRAPH);
+    if (scene->clearance_mm < 0) return fail(DPSO_E_INVAL, "clearance must be >= 0");
+    const int64_t lim = int64_t(1) << 26;
+    for (int64_t i = 0; i < 3 * int64_t(n); ++i)
+        if (scene->vp_mm[i] <= -lim || scene->vp_mm[i] >= lim)
+            return fail(DPSO_E_RANGE, "viewpoint coordinate %d outside (-2^26, 2^26)", scene->vp_mm[i]);
+    for (int32_t b = 0; b < nb; ++b)
+        for (int a = 0; a < 3; ++a) {
+            const int64_t lo = scene->boxes_mm[6 * b + a], hi = scene->boxes_mm[6 * b + 3 + a];
+            if (lo > hi) return fail(DPSO_E_INVAL, "box %d has lo > hi on axis %d", b, a);
+            if (lo - scene->clearance_mm <= -lim || hi + scene->clearance_mm >= lim)
+                return fail(DPSO_E_RANGE, "inflated box %d outside (-2^26, 2^26)", b);
+        }
+    if (work_bytes < dpso::dist_work_bytes(n, nb))
+        return fail(DPSO_E_NOMEM, "workspace of %zu bytes, %zu needed", work_bytes,
+                    dpso::dist_work_bytes(n, nb));
+    int range_error = 0;
+    HIP_TRY(dpso::build_dist(scene->vp_mm, n, scene->boxes_mm, nb, scene->clearance_mm, d_dist, d_work,
+                             as_stream(stream), &range_error),
+            "build_dist");
+    if (range_error) return fail(DPSO_E_RANGE, "a finite path cost reaches DPSO_D_INF");
+    return ok();
+}
+
+dpso_status dpso_init_nn(const int32_t *d_dist, int32_t n, const dpso_params *params, void *d_state,
+                         size_t state_bytes, void *stream)
+{
+    dpso_status st = check_params(params, n);
+    if (st) return st;
+    if (!d_dist || !d_state) return fail(DPSO_E_INVAL, "d_dist and d_state must be non-NULL");
+    const dpso::Layout L = dpso::make_layout(n, params->swarm_size, params->max_generations + 1);
+    if (state_bytes < L.total)
+        return fail(DPSO_E_NOMEM, "state buffer of %zu bytes, %zu needed", state_bytes, L.total);
+    const dpso::View v = dpso::make_view(d_state, L);
+    HIP_TRY(dpso::launch_init(d_dist, v, kernel_params(params), L.cap, as_stream(stream)), "launch init");
+    return ok();
+}
+
+dpso_status dpso_run(const int32_t *d_dist, int32_t n, const dpso_params *params, void *d_state,
+                     size_t state_bytes, int32_t generations, void *stream)
+{
+    return run_impl(d_dist, n, params, d_state, state_bytes, generations, stream, nullptr);
+}
+
+dpso_status dpso_run_profiled(const int32_t *d_dist, int32_t n, const dpso_params *params, void *d_state,
+                              size_t state_bytes, int32_t generations, dpso_phase_times *times,
+                              void *stream)
+{
+    if (!times) return fail(DPSO_E_INVAL, "times is NULL");
+    return run_impl(d_dist, n, params, d_state, state_bytes, generations, stream, times);
+}
+
+dpso_status dpso_get_info(const void *d_state, dpso_info *info, void *stream)
+{
+    if (!info) return fail(DPSO_E_INVAL, "info is NULL");
+    dpso::Hdr h;
+    dpso_status st = read_header(d_state, &h, as_stream(stream));
+    if (st) return st;
+    info->n = h.n;
+    info->swarm_size = h.S;
+    info->trace_capacity = h.cap;
+    info->generation = h.t;
+    info->stall = h.stall;
+    info->done = h.done;
+    info->best_cost = h.FG;
+    info->sweeps = int64_t(h.n_sweeps);
+    info->moves = int64_t(h.n_moves);
+    info->reshuffled = int64_t(h.n_reshuffled);
+    return ok();
+}
+
+dpso_status dpso_get_best(const void *d_state, int32_t *h_tour, int64_t *h_cost, int32_t *h_generation,
+                          int64_t *h_trace, void *stream)
+{
+    hipStream_t s = as_stream(stream);
+    dpso::Hdr h;
+    dpso_status st = read_header(d_state, &h, s);
+    if (st) return st;
+    const dpso::Layout L = dpso::make_layout(h.n, h.S, h.cap);
+    const char *base = static_cast<const char *>(d_state);
+    std::vector<uint16_t> g(size_t(h.n));
+    HIP_TRY(hipMemcpyAsync(g.data(), base + L.G, size_t(h.n) * 2, hipMemcpyDeviceToHost, s), "copy G");
+    if (h_trace)
+        HIP_TRY(hipMemcpyAsync(h_trace, base + L.trace, size_t(h.t + 1) * 8, hipMemcpyDeviceToHost, s),
+                "copy trace");
+    HIP_TRY(hipStreamSynchronize(s), "synchronise stream");
+    if (h_tour)
+        for (int32_t k = 0; k < h.n; ++k) h_tour[k] = g[k];
+    if (h_cost) *h_cost = h.FG;
+    if (h_generation) *h_generation = h.t;
+    return ok();
+}
+
+dpso_status dpso_export_state(const void *d_state, int32_t n, int32_t swarm_size, dpso_host_state *out,
+                              void *stream)
+{
+    if (!out || !out->X || !out->P || !out->V || !out->vlen || !out->F || !out->FP || !out->G)
+        return fail(DPSO_E_INVAL, "every array of the host state must be non-NULL");
+    hipStream_t s = as_stream(stream);
+    dpso::Hdr h;
+    dpso_status st = read_header(d_state, &h, s);
+    if (st) return st;
+    if (h.n != n || h.S != swarm_size)
+        return fail(DPSO_E_STATE, "state holds n = %d, swarm %d; asked for n = %d, swarm %d", h.n, h.S, n,
+                    swarm_size);
+    const dpso::Layout L = dpso::make_layout(h.n, h.S, h.cap);
+    const char *b = static_cast<const char *>(d_state);
+    const size_t S = size_t(h.S);
+    HIP_TRY(hipMemcpy2DAsync(out->X, size_t(n) * 2, b + L.X, size_t(L.ns) * 2, size_t(n) * 2, S,
+                             hipMemcpyDeviceToHost, s), "copy X");
+    HIP_TRY(hipMemcpy2DAsync(out->P, size_t(n) * 2, b + L.P, size_t(L.ns) * 2, size_t(n) * 2, S,
+                             hipMemcpyDeviceToHost, s), "copy P");
+    HIP_TRY(hipMemcpy2DAsync(out->V, size_t(n) * 4, b + L.V, size_t(L.ns) * 4, size_t(n) * 4, S,
+                             hipMemcpyDeviceToHost, s), "copy V");
+    HIP_TRY(hipMemcpyAsync(out->vlen, b + L.VL, S * 4, hipMemcpyDeviceToHost, s), "copy VL");
+    HIP_TRY(hipMemcpyAsync(out->F, b + L.F, S * 8, hipMemcpyDeviceToHost, s), "copy F");
+    HIP_TRY(hipMemcpyAsync(out->FP, b + L.FP, S * 8, hipMemcpyDeviceToHost, s), "copy FP");
+    HIP_TRY(hipMemcpyAsync(out->G, b + L.G, size_t(n) * 2, hipMemcpyDeviceToHost, s), "copy G");
+    if (out->trace)
+        HIP_TRY(hipMemcpyAsync(out->trace, b + L.trace, size_t(h.t + 1) * 8, hipMemcpyDeviceToHost, s),
+                "copy trace");
+    HIP_TRY(hipStreamSynchronize(s), "synchronise stream");
+    out->generation = h.t;
+    out->stall = h.stall;
+    out->done = h.done;
+    out->best_cost = h.FG;
+    return ok();
+}
+
+dpso_status dpso_import_state(void *d_state, size_t state_bytes, int32_t n, int32_t swarm_size,
+                              const dpso_host_state *in, void *stream)
+{
+    if (!in || !in->X || !in->P || !in->V || !in->vlen || !in->F || !in->FP || !in->G || !in->trace)
+        return fail(DPSO_E_INVAL, "every array of the host state must be non-NULL");
+    hipStream_t s = as_stream(stream);
+    dpso::Hdr h;
+    dpso_status st = read_header(d_state, &h, s);
+    if (st) return st;
+    if (h.n != n || h.S != swarm_size)
+        return fail(DPSO_E_STATE, "state holds n = %d, swarm %d; asked for n = %d, swarm %d", h.n, h.S, n,
+                    swarm_size);
+    const dpso::Layout L = dpso::make_layout(h.n, h.S, h.cap);
+    if (state_bytes < L.total) return fail(DPSO_E_NOMEM, "state buffer too small");
+    if (in->generation < 0 || in->generation >= h.cap)
+        return fail(DPSO_E_RANGE, "generation %d outside the trace capacity %d", in->generation, h.cap);
+    const size_t S = size_t(h.S);
+    std::vector<uint8_t> seen(static_cast<size_t>(n), 0);
+    auto is_perm = [&](const uint16_t *t) {
+        std::fill(seen.begin(), seen.end(), 0);
+        for (int32_t k = 0; k < n; ++k) {
+            if (t[k] >= n || seen[t[k]]) return false;
+            seen[t[k]] = 1;
+        }
+        return true;
+    };
+    for (size_t p = 0; p < S; ++p) {
+        if (!is_perm(in->X + p * n) || !is_perm(in->P + p * n))
+            return fail(DPSO_E_INVAL, "tour of particle %zu is not a permutation", p);
+        if (in->vlen[p] < 0 || in->vlen[p] > n - 1)
+            return fail(DPSO_E_INVAL, "velocity length of particle %zu out of range", p);
+        for (int32_t k = 0; k < 2 * in->vlen[p]; ++k)
+            if (in->V[p * n * 2 + k] >= n) return fail(DPSO_E_INVAL, "velocity label out of range");
+    }
+    if (!is_perm(in->G)) return fail(DPSO_E_INVAL, "global best is not a permutation");
+    char *b = static_cast<char *>(d_state);
+    HIP_TRY(hipMemcpy2DAsync(b + L.X, size_t(L.ns) * 2, in->X, size_t(n) * 2, size_t(n) * 2, S,
+                             hipMemcpyHostToDevice, s), "copy X");
+    HIP_TRY(hipMemcpy2DAsync(b + L.P, size_t(L.ns) * 2, in->P, size_t(n) * 2, size_t(n) * 2, S,
+                             hipMemcpyHostToDevice, s), "copy P");
+    HIP_TRY(hipMemcpy2DAsync(b + L.V, size_t(L.ns) * 4, in->V, size_t(n) * 4, size_t(n) * 4, S,
+                             hipMemcpyHostToDevice, s), "copy V");
+    HIP_TRY(hipMemcpyAsync(b + L.VL, in->vlen, S * 4, hipMemcpyHostToDevice, s), "copy VL");
+    HIP_TRY(hipMemcpyAsync(b + L.F, in->F, S * 8, hipMemcpyHostToDevice, s), "copy F");
+    HIP_TRY(hipMemcpyAsync(b + L.FP, in->FP, S * 8, hipMemcpyHostToDevice, s), "copy FP");
+    HIP_TRY(hipMemcpyAsync(b + L.G, in->G, size_t(n) * 2, hipMemcpyHostToDevice, s), "copy G");
+    HIP_TRY(hipMemcpyAsync(b + L.trace, in->trace, size_t(in->generation + 1) * 8, hipMemcpyHostToDevice, s),
+            "copy trace");
+    h.t = in->generation;
+    h.stall = in->stall;
+    h.done = in->done;
+    h.FG = in->best_cost;
+    h.improved = 0;
+    h.ee_ran = 0;
+    HIP_TRY(hipMemcpyAsync(d_state, &h, sizeof h, hipMemcpyHostToDevice, s), "write header");
+    HIP_TRY(hipStreamSynchronize(s), "synchronise stream");
+    return ok();
+}
+
+}  // extern "C"

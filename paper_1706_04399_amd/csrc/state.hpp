@@ -1,0 +1,103 @@
+// Layout of the swarm state buffer in device memory.
+//
+// Structure-of-arrays, every region 256-byte aligned:
+//   hdr    Header (generation counter, flags, global-best cost, counters)
+//   X, P   uint16 [S][ns]   current and personal-best tours (ns = n rounded up
+//                           to 64 labels, so each row starts 128-byte aligned)
+//   V      uint32 [S][ns]   velocity transpositions, label a | label b << 16
+//   VL     int32  [S]       velocity lengths
+//   F, FP  int64  [S]       costs of X and P
+//   G      uint16 [ns]      global-best tour
+//   trace  int64  [cap]     global-best cost after each generation
+//   flags  int32  [S]      mutation scratch: duplicate marks
+//   keep   int32  [S]      mutation scratch: kept marks
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+namespace dpso {
+
+constexpr uint32_t kMagic = 0x4f535044u;  // "DPSO"
+
+struct Hdr {
+    uint32_t magic;
+    int32_t n, S, cap;
+    int32_t t;         // generations completed
+    int32_t stall;     // generations without improvement of the global best
+    int32_t done;      // stop condition reached
+    int32_t improved;  // global best improved in the current generation
+    int32_t ee_ran;    // edge exchange runs in the current generation
+    int32_t err;       // non-zero: state rejected by a kernel
+    int32_t max_generations, stall_limit;
+    int64_t FG;        // cost of the global best
+    uint64_t n_sweeps, n_moves, n_reshuffled;
+};
+
+struct Layout {
+    int32_t n, S, cap, ns;
+    size_t hdr, X, P, V, VL, F, FP, G, trace, flags, keep, total;
+};
+
+inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+inline Layout make_layout(int32_t n, int32_t S, int32_t cap)
+{
+    Layout L{};
+    L.n = n; L.S = S; L.cap = cap;
+    L.ns = (n + 63) & ~63;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t at = o; o = align256(o + bytes); return at; };
+    L.hdr = take(sizeof(Hdr));
+    L.X = take(size_t(S) * L.ns * 2);
+    L.P = take(size_t(S) * L.ns * 2);
+    L.V = take(size_t(S) * L.ns * 4);
+    L.VL = take(size_t(S) * 4);
+    L.F = take(size_t(S) * 8);
+    L.FP = take(size_t(S) * 8);
+    L.G = take(size_t(L.ns) * 2);
+    L.trace = take(size_t(cap) * 8);
+    L.flags = take(size_t(S) * 4);
+    L.keep = take(size_t(S) * 4);
+    L.total = o;
+    return L;
+}
+
+// Device pointers into one state buffer.
+struct View {
+    Hdr *hdr;
+    uint16_t *X, *P, *G;
+    uint32_t *V;
+    int32_t *VL, *flags, *keep;
+    int64_t *F, *FP, *trace;
+    int32_t n, S, ns;
+};
+
+inline View make_view(void *base, const Layout &L)
+{
+    char *b = static_cast<char *>(base);
+    View v;
+    v.hdr = reinterpret_cast<Hdr *>(b + L.hdr);
+    v.X = reinterpret_cast<uint16_t *>(b + L.X);
+    v.P = reinterpret_cast<uint16_t *>(b + L.P);
+    v.V = reinterpret_cast<uint32_t *>(b + L.V);
+    v.VL = reinterpret_cast<int32_t *>(b + L.VL);
+    v.F = reinterpret_cast<int64_t *>(b + L.F);
+    v.FP = reinterpret_cast<int64_t *>(b + L.FP);
+    v.G = reinterpret_cast<uint16_t *>(b + L.G);
+    v.trace = reinterpret_cast<int64_t *>(b + L.trace);
+    v.flags = reinterpret_cast<int32_t *>(b + L.flags);
+    v.keep = reinterpret_cast<int32_t *>(b + L.keep);
+    v.n = L.n; v.S = L.S; v.ns = L.ns;
+    return v;
+}
+
+// Swarm parameters as the kernels see them.
+struct KParams {
+    uint64_t seed, instance;
+    uint32_t w_q16, phi1_q16, phi2_q16;
+    int32_t mutation_period, ee_trigger, ee_max_moves, stall_limit, max_generations;
+    int32_t det_count;  // number of nearest-neighbour seeded particles
+};
+
+}  // namespace dpso

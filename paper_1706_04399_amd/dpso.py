@@ -1,0 +1,256 @@
+"""Python binding of the C ABI in ``include/dpso.h`` (argument marshalling only).
+
+Device memory comes from torch tensors on the current HIP device and work is
+enqueued on torch's current stream unless a stream is given. Every step of
+the swarm runs in ``libdpso.so``; if the library is missing this module
+raises instead of computing anything itself.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch  # loaded first so libdpso binds to the HIP runtime torch already uses
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libdpso.so")
+
+OK, E_INVAL, E_RANGE, E_NOMEM, E_DEVICE, E_STATE = 0, -1, -2, -3, -4, -5
+D_INF = (1 << 28) - 1
+MAX_N = 4096
+MAX_SWARM = 65536
+EE_OFF, EE_ON_STALL, EE_ALWAYS = 0, 1, 2
+
+
+class DpsoError(RuntimeError):
+    def __init__(self, status: int, text: str):
+        super().__init__(f"dpso status {status}: {text}")
+        self.status = status
+
+
+class Scene(C.Structure):
+    _fields_ = [("vp_mm", C.c_void_p), ("n", C.c_int32), ("boxes_mm", C.c_void_p),
+                ("n_boxes", C.c_int32), ("clearance_mm", C.c_int32)]
+
+
+class Params(C.Structure):
+    _fields_ = [("swarm_size", C.c_int32), ("max_generations", C.c_int32),
+                ("w_q16", C.c_uint32), ("phi1_q16", C.c_uint32), ("phi2_q16", C.c_uint32),
+                ("mutation_period", C.c_int32), ("ee_trigger", C.c_int32),
+                ("ee_max_moves", C.c_int32), ("stall_limit", C.c_int32),
+                ("det_permille", C.c_int32), ("seed", C.c_uint64), ("instance", C.c_uint64)]
+
+
+class Info(C.Structure):
+    _fields_ = [("n", C.c_int32), ("swarm_size", C.c_int32), ("trace_capacity", C.c_int32),
+                ("generation", C.c_int32), ("stall", C.c_int32), ("done", C.c_int32),
+                ("best_cost", C.c_int64), ("sweeps", C.c_int64), ("moves", C.c_int64),
+                ("reshuffled", C.c_int64)]
+
+
+class PhaseTimes(C.Structure):
+    _fields_ = [("ms_total", C.c_float), ("ms_move", C.c_float), ("ms_mutation", C.c_float),
+                ("ms_gbest", C.c_float), ("ms_exchange", C.c_float), ("ms_control", C.c_float),
+                ("generations", C.c_int32), ("exchange_launches", C.c_int32)]
+
+
+class HostState(C.Structure):
+    _fields_ = [("X", C.c_void_p), ("P", C.c_void_p), ("V", C.c_void_p), ("vlen", C.c_void_p),
+                ("F", C.c_void_p), ("FP", C.c_void_p), ("G", C.c_void_p), ("trace", C.c_void_p),
+                ("generation", C.c_int32), ("stall", C.c_int32), ("done", C.c_int32),
+                ("best_cost", C.c_int64)]
+
+
+EXPORTS = {
+    "dpso_version": (C.c_char_p, []),
+    "dpso_last_error": (C.c_char_p, []),
+    "dpso_validate_params": (C.c_int32, [C.c_void_p, C.c_int32]),
+    "dpso_state_bytes": (C.c_size_t, [C.c_int32, C.c_int32, C.c_int32]),
+    "dpso_dist_work_bytes": (C.c_size_t, [C.c_int32, C.c_int32]),
+    "dpso_build_dist": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+    "dpso_init_nn": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_size_t,
+                                 C.c_void_p]),
+    "dpso_run": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_size_t,
+                             C.c_int32, C.c_void_p]),
+    "dpso_run_profiled": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_size_t,
+                                      C.c_int32, C.c_void_p, C.c_void_p]),
+    "dpso_get_info": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "dpso_get_best": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                  C.c_void_p]),
+    "dpso_export_state": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p]),
+    "dpso_import_state": (C.c_int32, [C.c_void_p, C.c_size_t, C.c_int32, C.c_int32, C.c_void_p,
+                                      C.c_void_p]),
+}
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise RuntimeError(f"{_LIB_PATH} is missing: build it with "
+                               "`python -m paper_1706_04399_amd.build` (no fallback exists)")
+        L = C.CDLL(_LIB_PATH, mode=C.RTLD_GLOBAL)
+        for name, (res, args) in EXPORTS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != OK:
+        raise DpsoError(status, lib().dpso_last_error().decode())
+
+
+def _stream(stream):
+    if stream is None:
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, torch.cuda.Stream):
+        return C.c_void_p(stream.cuda_stream)
+    return C.c_void_p(int(stream))
+
+
+def _params(p) -> Params:
+    if isinstance(p, Params):
+        return p
+    return Params(**{k: int(p[k]) for k, _ in Params._fields_})
+
+
+def _dev(t: torch.Tensor, dtype) -> C.c_void_p:
+    if not (t.is_cuda and t.dtype == dtype and t.is_contiguous()):
+        raise ValueError(f"expected a contiguous {dtype} tensor on the GPU")
+    return C.c_void_p(t.data_ptr())
+
+
+def version() -> str:
+    return lib().dpso_version().decode()
+
+
+def validate_params(params, n: int):
+    _check(lib().dpso_validate_params(C.byref(_params(params)), n))
+
+
+def state_bytes(n: int, swarm_size: int, max_generations: int) -> int:
+    return int(lib().dpso_state_bytes(n, swarm_size, max_generations))
+
+
+def dist_work_bytes(n: int, n_boxes: int) -> int:
+    return int(lib().dpso_dist_work_bytes(n, n_boxes))
+
+
+def build_dist(scene, out: torch.Tensor | None = None, stream=None, device=None) -> torch.Tensor:
+    """Travelling-cost matrix of a scene as an int32 [n, n] GPU tensor."""
+    vp = np.ascontiguousarray(scene.vp_mm, dtype=np.int32)
+    bx = np.ascontiguousarray(scene.boxes_mm, dtype=np.int32)
+    n, nb = vp.shape[0], bx.shape[0]
+    dev = device if device is not None else (out.device if out is not None else "cuda")
+    if out is None:
+        out = torch.empty((n, n), dtype=torch.int32, device=dev)
+    work = torch.empty(max(dist_work_bytes(n, nb), 1), dtype=torch.uint8, device=dev)
+    sc = Scene(vp.ctypes.data, n, bx.ctypes.data if nb else None, nb, int(scene.clearance_mm))
+    _check(lib().dpso_build_dist(C.byref(sc), _dev(out, torch.int32), C.c_void_p(work.data_ptr()),
+                                 work.numel(), _stream(stream)))
+    return out
+
+
+def new_state(n: int, params, device="cuda") -> torch.Tensor:
+    p = _params(params)
+    nbytes = state_bytes(n, p.swarm_size, p.max_generations)
+    if nbytes == 0:
+        raise DpsoError(E_RANGE, f"no state layout for n={n}, swarm={p.swarm_size}")
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+def init_nn(D: torch.Tensor, params, state: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    n = D.shape[0]
+    if state is None:
+        state = new_state(n, params, D.device)
+    _check(lib().dpso_init_nn(_dev(D, torch.int32), n, C.byref(_params(params)),
+                              _dev(state, torch.uint8), state.numel(), _stream(stream)))
+    return state
+
+
+def run(D: torch.Tensor, params, state: torch.Tensor, generations: int, stream=None):
+    n = D.shape[0]
+    _check(lib().dpso_run(_dev(D, torch.int32), n, C.byref(_params(params)),
+                          _dev(state, torch.uint8), state.numel(), int(generations),
+                          _stream(stream)))
+
+
+def run_profiled(D: torch.Tensor, params, state: torch.Tensor, generations: int,
+                 stream=None) -> dict:
+    """run() with HIP events between phases; returns device ms per phase."""
+    n = D.shape[0]
+    t = PhaseTimes()
+    _check(lib().dpso_run_profiled(_dev(D, torch.int32), n, C.byref(_params(params)),
+                                   _dev(state, torch.uint8), state.numel(), int(generations),
+                                   C.byref(t), _stream(stream)))
+    return {k: getattr(t, k) for k, _ in PhaseTimes._fields_}
+
+
+def get_info(state: torch.Tensor, stream=None) -> dict:
+    info = Info()
+    _check(lib().dpso_get_info(_dev(state, torch.uint8), C.byref(info), _stream(stream)))
+    return {k: getattr(info, k) for k, _ in Info._fields_}
+
+
+def get_best(state: torch.Tensor, stream=None):
+    """(tour int32[n], cost, generation, trace int64[generation + 1])."""
+    info = get_info(state, stream)
+    tour = np.zeros(info["n"], np.int32)
+    trace = np.zeros(info["generation"] + 1, np.int64)
+    cost, gen = C.c_int64(), C.c_int32()
+    _check(lib().dpso_get_best(_dev(state, torch.uint8), tour.ctypes.data, C.byref(cost),
+                               C.byref(gen), trace.ctypes.data, _stream(stream)))
+    return tour, cost.value, gen.value, trace[: gen.value + 1]
+
+
+def export_state(state: torch.Tensor, n: int, swarm_size: int, stream=None) -> dict:
+    info = get_info(state, stream)
+    a = dict(X=np.zeros((swarm_size, n), np.uint16), P=np.zeros((swarm_size, n), np.uint16),
+             V=np.zeros((swarm_size, n, 2), np.uint16), vlen=np.zeros(swarm_size, np.int32),
+             F=np.zeros(swarm_size, np.int64), FP=np.zeros(swarm_size, np.int64),
+             G=np.zeros(n, np.uint16), trace=np.zeros(info["trace_capacity"], np.int64))
+    hs = HostState(*[a[k].ctypes.data for k in ("X", "P", "V", "vlen", "F", "FP", "G", "trace")])
+    _check(lib().dpso_export_state(_dev(state, torch.uint8), n, swarm_size, C.byref(hs),
+                                   _stream(stream)))
+    a.update(generation=hs.generation, stall=hs.stall, done=hs.done, best_cost=hs.best_cost)
+    a["trace"] = a["trace"][: hs.generation + 1]
+    return a
+
+
+def import_state(state: torch.Tensor, n: int, swarm_size: int, host: dict, stream=None):
+    arr = {k: np.ascontiguousarray(host[k], dtype=dt) for k, dt in
+           (("X", np.uint16), ("P", np.uint16), ("V", np.uint16), ("vlen", np.int32),
+            ("F", np.int64), ("FP", np.int64), ("G", np.uint16), ("trace", np.int64))}
+    hs = HostState(*[arr[k].ctypes.data for k in ("X", "P", "V", "vlen", "F", "FP", "G", "trace")],
+                   int(host["generation"]), int(host["stall"]), int(host["done"]),
+                   int(host["best_cost"]))
+    _check(lib().dpso_import_state(_dev(state, torch.uint8), state.numel(), n, swarm_size,
+                                   C.byref(hs), _stream(stream)))
+
+
+class Solver:
+    """One swarm on one GPU: distance matrix and state stay in device memory."""
+
+    def __init__(self, scene=None, params=None, D: torch.Tensor | None = None, device="cuda",
+                 stream=None):
+        self.params = dict(params)
+        self.stream = stream
+        self.D = D if D is not None else build_dist(scene, stream=stream, device=device)
+        self.n = self.D.shape[0]
+        self.state = init_nn(self.D, self.params, stream=stream)
+
+    def run(self, generations: int):
+        run(self.D, self.params, self.state, generations, self.stream)
+        return self
+
+    def best(self):
+        return get_best(self.state, self.stream)
+
+    def info(self):
+        return get_info(self.state, self.stream)

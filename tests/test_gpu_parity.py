@@ -1,0 +1,210 @@
+"""Parity of the HIP library with the CPU oracle (bit-exact: all integer).
+
+Each test feeds both sides the same seeded inputs and compares the whole
+swarm state (tours, personal bests, velocities, costs, global best, trace,
+counters of generations) element by element.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1706_04399_amd import scenes
+from parity import as_host, mismatches, note, synthetic_state
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dp():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1706_04399_amd import dpso
+    dpso.lib()
+    return dpso
+
+
+def _dev(D):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(D, dtype=np.int32)).cuda()
+
+
+def _golden_detour_scene():
+    from conftest import golden_lines
+    rows = golden_lines("box_detour.txt")
+    vp = [[int(v) for v in r[1:]] for r in rows if r[0] == "vp"]
+    box = [[int(v) for v in r[1:]] for r in rows if r[0] == "box"]
+    return scenes.Scene(np.array(vp), np.array(box), 500)
+
+
+DIST_CASES = {
+    "facade30": lambda: scenes.workload(1)[0],
+    "bridge200": lambda: scenes.workload(2)[0],
+    "facade1000": lambda: scenes.workload(3)[0],
+    "random50_5boxes": lambda: scenes.random_points(50, seed=3, n_boxes=5),
+    "circle64": lambda: scenes.circle(64),
+    "grid8x6": lambda: scenes.grid(8, 6),
+    "detour": _golden_detour_scene,
+    "single": lambda: scenes.line([7]),
+    "batch_item_3": lambda: scenes.batch_instance(3),
+}
+
+
+@pytest.mark.parametrize("name", list(DIST_CASES))
+def test_build_dist_matches_oracle(dp, name):
+    sc = DIST_CASES[name]()
+    note(f"build_dist {name} n={sc.n} boxes={len(sc.boxes_mm)}")
+    got = dp.build_dist(sc).cpu().numpy()
+    assert np.array_equal(got, oracle.build_dist(sc))
+
+
+def test_build_dist_unreachable_pair(dp):
+    slabs = [(-3000, -3000, -3000, -2000, 3000, 3000), (2000, -3000, -3000, 3000, 3000, 3000),
+             (-3000, -3000, -3000, 3000, -2000, 3000), (-3000, 2000, -3000, 3000, 3000, 3000),
+             (-3000, -3000, -3000, 3000, 3000, -2000), (-3000, -3000, 2000, 3000, 3000, 3000)]
+    sc = scenes.Scene(np.array([(0, 0, 0), (10000, 0, 0), (10000, 5000, 0)]), np.array(slabs), 0)
+    note("build_dist sealed viewpoint")
+    got = dp.build_dist(sc).cpu().numpy()
+    assert np.array_equal(got, oracle.build_dist(sc))
+    assert got[0, 1] == dp.D_INF
+
+
+def lockstep(dp, D, prm, checkpoints, label):
+    """Runs library and oracle from the same initial swarm, comparing the whole
+    state at each checkpoint generation."""
+    note(f"{label}: init n={D.shape[0]} S={prm['swarm_size']}")
+    Dg = _dev(D)
+    state = dp.init_nn(Dg, prm)
+    ost = oracle.new_state(D, prm)
+    bad = mismatches(dp.export_state(state, D.shape[0], prm["swarm_size"]), ost)
+    assert not bad, f"after init: {bad}"
+    done = 0
+    for cp in checkpoints:
+        note(f"{label}: run to generation {cp}")
+        dp.run(Dg, prm, state, cp - done)
+        oracle.run(D, prm, ost, cp - done)
+        done = cp
+        bad = mismatches(dp.export_state(state, D.shape[0], prm["swarm_size"]), ost)
+        assert not bad, f"generation {cp}: {bad}"
+    info = dp.get_info(state)
+    assert (info["sweeps"], info["moves"], info["reshuffled"]) == \
+        (ost.n_sweeps, ost.n_moves, ost.n_reshuffled)
+    tour, cost, gen, trace = dp.get_best(state)
+    assert np.array_equal(tour, ost.G) and cost == ost.FG and gen == ost.t
+    return state, ost
+
+
+def test_workload1_full_run(dp):
+    sc, prm = scenes.workload(1)
+    D = oracle.build_dist(sc)
+    lockstep(dp, D, prm, [1, 2, 3, 4, 5, 6, 10, 50, 100, 200], "facade30")
+
+
+def test_workload2_full_run(dp):
+    sc, prm = scenes.workload(2)
+    D = oracle.build_dist(sc)
+    lockstep(dp, D, prm, [1, 2, 3, 30, 300, 1000], "bridge200")
+
+
+def test_workload3_first_generations(dp):
+    """The benchmark's workload and launch configuration, first generations."""
+    sc, prm = scenes.workload(3)
+    D = oracle.build_dist(sc)
+    lockstep(dp, D, prm, [1, 3], "facade1000")
+
+
+def test_workload3_late_generation_from_synthetic_state(dp):
+    """One mutation generation (t = 1500) at full size from a seeded mid-run state."""
+    sc, prm = scenes.workload(3)
+    D = oracle.build_dist(sc)
+    st = synthetic_state(D, prm, t=1499, seed=5)
+    Dg = _dev(D)
+    state = dp.new_state(D.shape[0], prm)
+    dp.init_nn(Dg, prm, state)
+    note("facade1000: import synthetic state at t=1499")
+    dp.import_state(state, D.shape[0], prm["swarm_size"], as_host(st))
+    dp.run(Dg, prm, state, 1)
+    oracle.run(D, prm, st, 1)
+    bad = mismatches(dp.export_state(state, D.shape[0], prm["swarm_size"]), st)
+    assert not bad, bad
+
+
+EDGE = [
+    # (name, n, S, gens, overrides)
+    ("n1", 1, 3, 6, {}),
+    ("n2", 2, 5, 6, {}),
+    ("n3", 3, 4, 6, {}),
+    ("n4", 4, 7, 9, dict(ee_trigger=2)),
+    ("n5_S1", 5, 1, 9, dict(ee_trigger=2)),
+    ("n63", 63, 33, 12, {}),
+    ("n64", 64, 64, 12, dict(ee_trigger=2, ee_max_moves=0)),
+    ("n65", 65, 65, 12, dict(det_permille=1000)),
+    ("n129_S257", 129, 257, 9, dict(det_permille=0, ee_trigger=2)),
+    ("ee_off", 40, 50, 12, dict(ee_trigger=0)),
+    ("no_mutation", 40, 50, 12, dict(mutation_period=0)),
+    ("stall_limit", 20, 16, 60, dict(stall_limit=3)),
+    ("w1_phi04", 50, 100, 12, dict(w=1.0, phi1=0.4, phi2=0.4)),
+    ("coef_max", 50, 30, 9, dict(w=2.0, phi1=2.0, phi2=2.0)),
+]
+
+
+@pytest.mark.parametrize("name,n,S,gens,kw", EDGE, ids=[e[0] for e in EDGE])
+def test_edge_cases(dp, name, n, S, gens, kw):
+    sc = scenes.random_points(n, seed=n + S, n_boxes=2 if n > 3 else 0)
+    D = oracle.build_dist(sc)
+    prm = scenes.swarm_params(S, gens, seed=17, instance=n, **kw)
+    lockstep(dp, D, prm, sorted({1, 2, 3, gens // 2 or 1, gens}), name)
+
+
+def test_collapsed_swarm_mutation(dp):
+    """All particles identical at a mutation generation: one is kept."""
+    n, S = 48, 96
+    D = oracle.build_dist(scenes.random_points(n, seed=2, n_boxes=3))
+    prm = scenes.swarm_params(S, 10, seed=3)
+    st = synthetic_state(D, prm, t=2, seed=9)
+    st.X[:] = st.X[0]
+    st.F[:] = st.F[0]
+    st.P[:] = st.X[0]
+    st.FP[:] = st.F[0]
+    st.G[:] = st.X[0]
+    st.FG = int(st.F[0])
+    st.trace[:3] = st.FG
+    st.VL[:] = 0
+    Dg = _dev(D)
+    state = dp.init_nn(Dg, prm)
+    dp.import_state(state, n, S, as_host(st))
+    note("collapsed swarm: generation 3")
+    dp.run(Dg, prm, state, 1)
+    oracle.run(D, prm, st, 1)
+    bad = mismatches(dp.export_state(state, n, S), st)
+    assert not bad, bad
+
+
+def test_split_run_equals_single_run(dp):
+    sc, prm = scenes.workload(1)
+    D = oracle.build_dist(sc)
+    Dg = _dev(D)
+    a = dp.init_nn(Dg, prm)
+    dp.run(Dg, prm, a, 37)
+    b = dp.init_nn(Dg, prm)
+    dp.run(Dg, prm, b, 20)
+    dp.run(Dg, prm, b, 17)
+    ea, eb = dp.export_state(a, sc.n, 64), dp.export_state(b, sc.n, 64)
+    for k in ea:
+        if k != "V":
+            assert np.array_equal(np.asarray(ea[k]), np.asarray(eb[k])), k
+    for p in range(64):      # slots past a velocity's length are unused
+        L = ea["vlen"][p]
+        assert np.array_equal(ea["V"][p, :L], eb["V"][p, :L]), p
+
+
+def test_state_mismatch_is_reported(dp):
+    sc, prm = scenes.workload(1)
+    D = oracle.build_dist(sc)
+    Dg = _dev(D)
+    state = dp.init_nn(Dg, prm)
+    other = dict(prm, swarm_size=32)
+    dp.run(Dg, other, state, 1)   # header says S = 64: the device rejects it
+    with pytest.raises(dp.DpsoError) as ei:
+        dp.get_info(state)
+    assert ei.value.status == dp.E_STATE

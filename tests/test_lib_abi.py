@@ -1,0 +1,106 @@
+"""The HIP library loads, exports every declared entry point and validates
+its arguments on the host (no device work, so these run without a GPU)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from conftest import ROOT
+
+HEADER = os.path.join(ROOT, "include", "dpso.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(dpso_[a-z_0-9]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def dp():
+    from paper_1706_04399_amd import dpso
+    dpso.lib()
+    return dpso
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("dpso_build_dist", "dpso_init_nn", "dpso_run", "dpso_get_best"):
+        assert required in names
+
+
+def test_every_declared_symbol_is_exported(dp):
+    raw = C.CDLL(dp._LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(raw, name), name
+    assert set(declared_functions()) <= set(dp.EXPORTS)
+
+
+def test_binding_covers_exports(dp):
+    assert set(dp.EXPORTS) == set(declared_functions())
+
+
+def _params(**kw):
+    from paper_1706_04399_amd import scenes
+    return scenes.swarm_params(64, 200, **kw)
+
+
+def test_validation_errors(dp):
+    dp.validate_params(_params(), 30)
+    bad = [(dict(swarm_size=0), 30, dp.E_INVAL), (dict(swarm_size=65537), 30, dp.E_INVAL),
+           (dict(w_q16=131073), 30, dp.E_INVAL), (dict(ee_trigger=3), 30, dp.E_INVAL),
+           (dict(det_permille=1001), 30, dp.E_INVAL), (dict(mutation_period=-1), 30, dp.E_INVAL),
+           (dict(ee_max_moves=-1), 30, dp.E_INVAL), (dict(), 0, dp.E_INVAL),
+           (dict(), dp.MAX_N + 1, dp.E_RANGE)]
+    for kw, n, code in bad:
+        p = _params()
+        p.update(kw)
+        with pytest.raises(dp.DpsoError) as ei:
+            dp.validate_params(p, n)
+        assert ei.value.status == code, (kw, n)
+        assert dp.lib().dpso_last_error()
+
+
+def test_state_bytes(dp):
+    assert dp.state_bytes(0, 1, 1) == 0
+    assert dp.state_bytes(10, 0, 1) == 0
+    assert dp.state_bytes(dp.MAX_N + 1, 1, 1) == 0
+    a = dp.state_bytes(1000, 4096, 2000)
+    # tours, personal bests and velocities dominate: 2 + 2 + 4 bytes per label
+    assert 4096 * 1024 * 8 <= a < 4096 * 1024 * 8 + (1 << 20)
+
+
+def test_calls_reject_null_pointers_before_device_work(dp):
+    L = dp.lib()
+    p = dp._params(_params())
+    assert L.dpso_init_nn(None, 30, C.byref(p), None, 0, None) == dp.E_INVAL
+    assert L.dpso_run(None, 30, C.byref(p), None, 0, 1, None) == dp.E_INVAL
+    assert L.dpso_build_dist(None, None, None, 0, None) == dp.E_INVAL
+    assert L.dpso_get_info(None, None, None) == dp.E_INVAL
+    # state buffer too small is caught on the host
+    fake = C.c_void_p(0x1000)
+    need = dp.state_bytes(30, 64, 200)
+    assert L.dpso_init_nn(fake, 30, C.byref(p), fake, need - 1, None) == dp.E_NOMEM
+    assert L.dpso_run(fake, 30, C.byref(p), fake, need - 1, 1, None) == dp.E_NOMEM
+    assert L.dpso_run(fake, 30, C.byref(p), fake, need, -1, None) == dp.E_INVAL
+
+
+def test_build_dist_validation(dp):
+    import numpy as np
+    L = dp.lib()
+    vp = np.array([[0, 0, 0], [1 << 26, 0, 0]], np.int32)
+    sc = dp.Scene(vp.ctypes.data, 2, None, 0, 0)
+    fake = C.c_void_p(0x1000)
+    assert L.dpso_build_dist(C.byref(sc), fake, fake, 1 << 20, None) == dp.E_RANGE
+    vp = np.array([[0, 0, 0], [5, 0, 0]], np.int32)
+    box = np.array([[5, 5, 5, 0, 0, 0]], np.int32)   # lo > hi
+    sc = dp.Scene(vp.ctypes.data, 2, box.ctypes.data, 1, 0)
+    assert L.dpso_build_dist(C.byref(sc), fake, fake, 1 << 20, None) == dp.E_INVAL
+    sc = dp.Scene(vp.ctypes.data, 2, None, 0, 0)
+    assert L.dpso_build_dist(C.byref(sc), fake, fake, 16, None) == dp.E_NOMEM
+
+
+def test_library_does_not_link_the_oracle(dp):
+    data = open(dp._LIB_PATH, "rb").read()
+    assert b"liboracle" not in data and b"or_build_dist" not in data
