@@ -203,8 +203,10 @@ dpso_status dpso_export_state(const void *d_state, int32_t n, int32_t swarm_size
 
 /* Replaces the swarm with host arrays (resume from a checkpoint). The state
  * must have been initialised for (n, swarm_size); trace entries
- * 0..generation are copied. Tours must be permutations of 0..n-1 and
- * vlen[p] <= n - 1 (checked on the host). Synchronises `stream`. */
+ * 0..generation are copied. Tours must be permutations of 0..n-1 and every
+ * velocity a canonical difference T - x of two tours, as the method
+ * produces (checked on the host; DPSO_E_INVAL otherwise). Synchronises
+ * `stream`. */
 dpso_status dpso_import_state(void *d_state, size_t state_bytes, int32_t n, int32_t swarm_size,
                               const dpso_host_state *in, void *stream);
 

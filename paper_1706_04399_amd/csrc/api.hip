@@ -95,6 +95,65 @@ dpso_status read_header(const void *d_state, dpso::Hdr *h, hipStream_t s)
     return DPSO_OK;
 }
 
+// Canonical difference to - from (positions scanned left to right; a
+// position holding the wrong label gets the right one by exchanging the two
+// labels). Writes the label pairs to out[2 * len]; returns len.
+int host_difference(const uint16_t *from, const uint16_t *to, int n, uint16_t *out,
+                    std::vector<uint16_t> &cur, std::vector<uint16_t> &pos)
+{
+    cur.assign(from, from + n);
+    pos.resize(size_t(n));
+    for (int i = 0; i < n; ++i) pos[cur[i]] = uint16_t(i);
+    int len = 0;
+    for (int q = 0; q < n; ++q) {
+        const uint16_t a = cur[q], b = to[q];
+        if (a == b) continue;
+        out[2 * len] = a;
+        out[2 * len + 1] = b;
+        ++len;
+        const uint16_t j = pos[b];
+        cur[q] = b;
+        cur[j] = a;
+        pos[b] = uint16_t(q);
+        pos[a] = j;
+    }
+    return len;
+}
+
+// A pair of tours (from, to) whose canonical difference is the given list:
+// to holds the second labels at positions 0..len-1 (then the other labels in
+// increasing order) and from is to with the exchanges undone in reverse
+// order. Returns false if the list is not a canonical difference.
+bool host_velocity_tours(const uint16_t *pairs, int len, int n, uint16_t *from, uint16_t *to)
+{
+    std::vector<uint8_t> used(static_cast<size_t>(n), 0);
+    for (int i = 0; i < len; ++i) {
+        const uint16_t a = pairs[2 * i], b = pairs[2 * i + 1];
+        if (a >= n || b >= n || a == b || used[b]) return false;
+        used[b] = 1;
+        to[i] = b;
+    }
+    int q = len;
+    for (int label = 0; label < n; ++label)
+        if (!used[label]) to[q++] = uint16_t(label);
+    std::vector<uint16_t> pos(static_cast<size_t>(n), 0);
+    for (int i = 0; i < n; ++i) {
+        from[i] = to[i];
+        pos[to[i]] = uint16_t(i);
+    }
+    for (int i = len - 1; i >= 0; --i) {
+        const uint16_t a = pairs[2 * i], b = pairs[2 * i + 1];
+        const uint16_t ia = pos[a], ib = pos[b];
+        from[ia] = b;
+        from[ib] = a;
+        pos[a] = ib;
+        pos[b] = ia;
+    }
+    std::vector<uint16_t> check(size_t(2 * n)), cur, scratch;
+    return host_difference(from, to, n, check.data(), cur, scratch) == len &&
+           std::equal(check.begin(), check.begin() + 2 * len, pairs);
+}
+
 // Event pool for dpso_run_profiled, reused across calls.
 std::mutex g_event_mutex;
 std::vector<hipEvent_t> g_events;
@@ -317,9 +376,10 @@ dpso_status dpso_export_state(const void *d_state, int32_t n, int32_t swarm_size
                              hipMemcpyDeviceToHost, s), "copy X");
     HIP_TRY(hipMemcpy2DAsync(out->P, size_t(n) * 2, b + L.P, size_t(L.ns) * 2, size_t(n) * 2, S,
                              hipMemcpyDeviceToHost, s), "copy P");
-    HIP_TRY(hipMemcpy2DAsync(out->V, size_t(n) * 4, b + L.V, size_t(L.ns) * 4, size_t(n) * 4, S,
-                             hipMemcpyDeviceToHost, s), "copy V");
-    HIP_TRY(hipMemcpyAsync(out->vlen, b + L.VL, S * 4, hipMemcpyDeviceToHost, s), "copy VL");
+    std::vector<uint16_t> vt(S * 2 * size_t(L.ns));
+    std::vector<int32_t> has_v(S);
+    HIP_TRY(hipMemcpyAsync(vt.data(), b + L.V, vt.size() * 2, hipMemcpyDeviceToHost, s), "copy V");
+    HIP_TRY(hipMemcpyAsync(has_v.data(), b + L.VL, S * 4, hipMemcpyDeviceToHost, s), "copy VL");
     HIP_TRY(hipMemcpyAsync(out->F, b + L.F, S * 8, hipMemcpyDeviceToHost, s), "copy F");
     HIP_TRY(hipMemcpyAsync(out->FP, b + L.FP, S * 8, hipMemcpyDeviceToHost, s), "copy FP");
     HIP_TRY(hipMemcpyAsync(out->G, b + L.G, size_t(n) * 2, hipMemcpyDeviceToHost, s), "copy G");
@@ -327,6 +387,13 @@ dpso_status dpso_export_state(const void *d_state, int32_t n, int32_t swarm_size
         HIP_TRY(hipMemcpyAsync(out->trace, b + L.trace, size_t(h.t + 1) * 8, hipMemcpyDeviceToHost, s),
                 "copy trace");
     HIP_TRY(hipStreamSynchronize(s), "synchronise stream");
+    std::vector<uint16_t> cur, pos;
+    for (size_t p = 0; p < S; ++p) {
+        uint16_t *row = out->V + p * size_t(n) * 2;
+        std::fill(row, row + size_t(n) * 2, uint16_t(0));
+        const uint16_t *from = vt.data() + p * 2 * L.ns;
+        out->vlen[p] = has_v[p] ? host_difference(from, from + L.ns, n, row, cur, pos) : 0;
+    }
     out->generation = h.t;
     out->stall = h.stall;
     out->done = h.done;
@@ -365,8 +432,14 @@ dpso_status dpso_import_state(void *d_state, size_t state_bytes, int32_t n, int3
             return fail(DPSO_E_INVAL, "tour of particle %zu is not a permutation", p);
         if (in->vlen[p] < 0 || in->vlen[p] > n - 1)
             return fail(DPSO_E_INVAL, "velocity length of particle %zu out of range", p);
-        for (int32_t k = 0; k < 2 * in->vlen[p]; ++k)
-            if (in->V[p * n * 2 + k] >= n) return fail(DPSO_E_INVAL, "velocity label out of range");
+    }
+    std::vector<uint16_t> vt(S * 2 * size_t(L.ns), 0);
+    std::vector<int32_t> has_v(S);
+    for (size_t p = 0; p < S; ++p) {
+        has_v[p] = in->vlen[p] > 0;
+        uint16_t *from = vt.data() + p * 2 * L.ns;
+        if (has_v[p] && !host_velocity_tours(in->V + p * size_t(n) * 2, in->vlen[p], n, from, from + L.ns))
+            return fail(DPSO_E_INVAL, "velocity of particle %zu is not a canonical difference of two tours", p);
     }
     if (!is_perm(in->G)) return fail(DPSO_E_INVAL, "global best is not a permutation");
     char *b = static_cast<char *>(d_state);
@@ -374,9 +447,8 @@ dpso_status dpso_import_state(void *d_state, size_t state_bytes, int32_t n, int3
                              hipMemcpyHostToDevice, s), "copy X");
     HIP_TRY(hipMemcpy2DAsync(b + L.P, size_t(L.ns) * 2, in->P, size_t(n) * 2, size_t(n) * 2, S,
                              hipMemcpyHostToDevice, s), "copy P");
-    HIP_TRY(hipMemcpy2DAsync(b + L.V, size_t(L.ns) * 4, in->V, size_t(n) * 4, size_t(n) * 4, S,
-                             hipMemcpyHostToDevice, s), "copy V");
-    HIP_TRY(hipMemcpyAsync(b + L.VL, in->vlen, S * 4, hipMemcpyHostToDevice, s), "copy VL");
+    HIP_TRY(hipMemcpyAsync(b + L.V, vt.data(), vt.size() * 2, hipMemcpyHostToDevice, s), "copy V");
+    HIP_TRY(hipMemcpyAsync(b + L.VL, has_v.data(), S * 4, hipMemcpyHostToDevice, s), "copy VL");
     HIP_TRY(hipMemcpyAsync(b + L.F, in->F, S * 8, hipMemcpyHostToDevice, s), "copy F");
     HIP_TRY(hipMemcpyAsync(b + L.FP, in->FP, S * 8, hipMemcpyHostToDevice, s), "copy FP");
     HIP_TRY(hipMemcpyAsync(b + L.G, in->G, size_t(n) * 2, hipMemcpyHostToDevice, s), "copy G");

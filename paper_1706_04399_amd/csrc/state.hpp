@@ -4,8 +4,9 @@
 //   hdr    Header (generation counter, flags, global-best cost, counters)
 //   X, P   uint16 [S][ns]   current and personal-best tours (ns = n rounded up
 //                           to 64 labels, so each row starts 128-byte aligned)
-//   V      uint32 [S][ns]   velocity transpositions, label a | label b << 16
-//   VL     int32  [S]       velocity lengths
+//   V      uint16 [S][2][ns] velocity as the pair of tours (from, to) whose
+//                           canonical difference to - from is the velocity
+//   VL     int32  [S]       1 if particle p has a velocity, 0 if it is empty
 //   F, FP  int64  [S]       costs of X and P
 //   G      uint16 [ns]      global-best tour
 //   trace  int64  [cap]     global-best cost after each generation
@@ -67,7 +68,7 @@ inline Layout make_layout(int32_t n, int32_t S, int32_t cap)
 struct View {
     Hdr *hdr;
     uint16_t *X, *P, *G;
-    uint32_t *V;
+    uint16_t *V;
     int32_t *VL, *flags, *keep;
     int64_t *F, *FP, *trace;
     int32_t n, S, ns;
@@ -80,7 +81,7 @@ inline View make_view(void *base, const Layout &L)
     v.hdr = reinterpret_cast<Hdr *>(b + L.hdr);
     v.X = reinterpret_cast<uint16_t *>(b + L.X);
     v.P = reinterpret_cast<uint16_t *>(b + L.P);
-    v.V = reinterpret_cast<uint32_t *>(b + L.V);
+    v.V = reinterpret_cast<uint16_t *>(b + L.V);
     v.VL = reinterpret_cast<int32_t *>(b + L.VL);
     v.F = reinterpret_cast<int64_t *>(b + L.F);
     v.FP = reinterpret_cast<int64_t *>(b + L.FP);

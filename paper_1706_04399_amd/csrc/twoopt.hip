@@ -98,8 +98,257 @@ __global__ __launch_bounds__(kThreads) void k_2opt_rows(const int32_t *__restric
     }
 }
 
+// ------------------------------------------------------------------------
+// One wavefront per particle, columns in registers.
+//
+// Lane l owns the columns c = l + 64 m (m < MB, n <= 64 MB). For row i of the
+// neighbourhood the wave gathers g_i[c] = D[x_i+1][x_c+1] from the row of
+// label x_i+1 staged in LDS: that is the second term of delta(i, c), and,
+// moved one column to the right (a wave rotation by one lane through DPP, the
+// column at lane 0 coming from lane 63 of the previous register), it is the
+// first term D[x_i+1][x_c+1] of delta(i+1, c+1). So every D entry of the
+// sweep is gathered once and each delta costs one LDS read and four VALU
+// operations. Row i only touches the blocks m >= (i+2)/64 (the triangle
+// j >= i+2): rows are processed in phases of 64 with the first block known
+// at compile time. Each lane keeps the minimum of its columns per row; the
+// best (delta, i) over rows and lanes is reduced at the end and the smallest
+// j of row i attaining it is found by recomputing that row.
+//
+// The pair (0, n-1) is left in the search: its edges share node x_0, and for
+// a symmetric D its delta is exactly 0, so it never wins against an
+// improving exchange and is never applied.
+//
+// The global loads of the next two rows are in flight while the current row
+// is evaluated; rows alternate between two LDS buffers at a fixed stride so
+// the gathers use immediate offsets. A single wave owns its LDS: LDS operations
+// of one wave complete in order, and a compiler fence keeps program order.
+namespace {
+
+constexpr int kPad = 1 << 30;  // edge cost of padding columns: never the minimum
+constexpr int kNone = 0x7fffffff;
+
+__device__ inline int rotate_up(int v)  // lane l receives lane l-1 (lane 0: lane 63)
+{
+    return __builtin_amdgcn_mov_dpp(v, 0x13C, 0xF, 0xF, false);
+}
+
+__device__ inline void compiler_fence() { __asm__ __volatile__("" ::: "memory"); }
+
+template <int MB>
+struct WaveCfg {
+    static constexpr int RV = (MB + 3) / 4;  // int4 per lane per row
+    static constexpr int BS = 256 * RV;      // row buffer stride (ints) >= 64 MB >= n
+};
+
+template <int MB, bool VEC4>
+struct RowPipe {
+    int4 v[WaveCfg<MB>::RV];
+
+    // issue the loads of one row of D (all in bounds: indices are clamped)
+    __device__ inline void load(const int32_t *__restrict__ src, int n)
+    {
+        const int lane = threadIdx.x;
+        if constexpr (VEC4) {
+            const int4 *s4 = reinterpret_cast<const int4 *>(src);
+            const int q = (n >> 2) - 1;
+#pragma unroll
+            for (int k = 0; k < WaveCfg<MB>::RV; ++k) v[k] = s4[min(lane + 64 * k, q)];
+        } else {
+#pragma unroll
+            for (int k = 0; k < WaveCfg<MB>::RV; ++k) {
+                const int b = 4 * (lane + 64 * k);
+                v[k].x = src[min(b + 0, n - 1)];
+                v[k].y = src[min(b + 1, n - 1)];
+                v[k].z = src[min(b + 2, n - 1)];
+                v[k].w = src[min(b + 3, n - 1)];
+            }
+        }
+    }
+
+    // write the row into a buffer of stride BS (entries past n are filler)
+    __device__ inline void store(int32_t *dst, int n) const
+    {
+        const int lane = threadIdx.x;
+        int4 *d4 = reinterpret_cast<int4 *>(dst);
+        if constexpr (VEC4) {
+            const int q = (n >> 2) - 1;
+#pragma unroll
+            for (int k = 0; k < WaveCfg<MB>::RV; ++k) d4[min(lane + 64 * k, q)] = v[k];
+        } else {
+#pragma unroll
+            for (int k = 0; k < WaveCfg<MB>::RV; ++k) d4[lane + 64 * k] = v[k];
+        }
+    }
+};
+
+template <int MB, bool VEC4>
+struct SweepState {
+    int loff[MB];  // x_c+1 of each owned column (label = index into a row)
+    int ne[MB];    // -D[x_c][x_c+1], kPad for padding columns
+    int g[MB];     // gathers of the previous row
+    RowPipe<MB, VEC4> pipe[2];  // rows x_i+1 and x_i+2 in flight (by row parity)
+    int best, best_i;
+};
+
+// Row i with the first active block M0 and buffer BI (0 for even rows).
+template <int MB, bool VEC4, int M0, int BI>
+__device__ __forceinline__ void sweep_row(SweepState<MB, VEC4> &S, const int32_t *__restrict__ D,
+                                          int32_t *bufs, const uint16_t *tour, int n, int i)
+{
+    constexpr int BS = WaveCfg<MB>::BS;
+    int32_t *cur = bufs + BI * BS;
+    const int32_t *prv = bufs + (1 - BI) * BS;
+    const int lane = threadIdx.x;
+    S.pipe[BI].store(cur, n);                  // row of x_i+1, loaded two rows ago
+    if (i + 5 <= n) S.pipe[BI].load(D + size_t(tour[i + 3]) * n, n);  // for row i+2
+    compiler_fence();
+    const int ei = prv[tour[i + 1]];           // D[x_i][x_i+1]
+    int carry = M0 > 0 ? rotate_up(S.g[M0 > 0 ? M0 - 1 : 0]) : 0;
+    int rm = kNone;
+#pragma unroll
+    for (int m = M0; m < MB; ++m) {
+        const int r = rotate_up(S.g[m]);
+        const int a = lane == 0 ? carry : r;
+        carry = r;
+        const int b = cur[S.loff[m]];
+        int d = a + b + S.ne[m];
+        if (m == M0) d = lane + 64 * M0 < i + 2 ? kNone : d;
+        rm = min(rm, d);
+        S.g[m] = b;
+    }
+    const int cand = rm - ei;
+    if (cand < S.best) {
+        S.best = cand;
+        S.best_i = i;
+    }
+}
+
+// Rows [64 M0 - 2, 64 M0 + 62) clipped to [0, n - 2), then the next phase.
+template <int MB, bool VEC4, int M0>
+__device__ __forceinline__ void sweep_phase(SweepState<MB, VEC4> &S, const int32_t *__restrict__ D,
+                                            int32_t *bufs, const uint16_t *tour, int n)
+{
+    const int lo = M0 == 0 ? 0 : 64 * M0 - 2;
+    const int hi = min(64 * M0 + 62, n - 2);
+    for (int i = lo; i < hi; i += 2) {  // lo is even: row parity picks the buffer
+        sweep_row<MB, VEC4, M0, 0>(S, D, bufs, tour, n, i);
+        if (i + 1 < hi) sweep_row<MB, VEC4, M0, 1>(S, D, bufs, tour, n, i + 1);
+    }
+    if constexpr (M0 + 1 < MB) {
+        if (hi < n - 2) sweep_phase<MB, VEC4, M0 + 1>(S, D, bufs, tour, n);
+    }
+}
+
+}  // namespace
+
+template <int MB, bool VEC4>
+__global__ __launch_bounds__(64) void k_2opt_wave(const int32_t *__restrict__ D, View st, KParams kp)
+{
+    constexpr int BS = WaveCfg<MB>::BS;
+    Hdr *h = st.hdr;
+    if (h->err || h->done || !h->ee_ran) return;
+    const int p = blockIdx.x, n = st.n, ns = st.ns, lane = threadIdx.x;
+    extern __shared__ __align__(16) unsigned char smem[];
+    int32_t *bufs = reinterpret_cast<int32_t *>(smem);  // [2][BS]
+    uint16_t *tour = reinterpret_cast<uint16_t *>(bufs + 2 * BS);
+    uint16_t *xg = st.X + size_t(p) * ns;
+    for (int k = lane; k < n; k += 64) tour[k] = xg[k];
+    compiler_fence();
+    int64_t F = st.F[p];
+    int moves = 0, sweeps = 0;
+    while (true) {
+        ++sweeps;
+        if (n < 4) break;
+        SweepState<MB, VEC4> S;
+#pragma unroll
+        for (int m = 0; m < MB; ++m) {
+            const int c = lane + 64 * m;
+            if (c < n) {
+                const int a = tour[c], b = tour[c + 1 < n ? c + 1 : 0];
+                S.loff[m] = b;
+                S.ne[m] = -D[size_t(a) * n + b];
+            } else {
+                S.loff[m] = 0;
+                S.ne[m] = kPad;
+            }
+        }
+        // g <- D[x_0][x_c+1]: the first term of row 0, one column to the right
+        S.pipe[0].load(D + size_t(tour[0]) * n, n);
+        S.pipe[0].store(bufs + BS, n);
+        compiler_fence();
+#pragma unroll
+        for (int m = 0; m < MB; ++m) S.g[m] = bufs[BS + S.loff[m]];
+        S.pipe[0].load(D + size_t(tour[1]) * n, n);
+        S.pipe[1].load(D + size_t(tour[2]) * n, n);
+        S.best = kNone;
+        S.best_i = 0;
+        sweep_phase<MB, VEC4, 0>(S, D, bufs, tour, n);
+        // best (delta, i) of the wave, smallest i on ties
+        const uint64_t key = (uint64_t(uint32_t(S.best) + 0x80000000u) << 32) | uint32_t(S.best_i);
+        const uint64_t win = wave_min_u64(key);
+        const int dbest = int(uint32_t(win >> 32) - 0x80000000u);
+        if (dbest >= 0) break;
+        const int bi = int(uint32_t(win));
+        // smallest j of row bi with delta(bi, j) == dbest
+        const int a0 = tour[bi], a1 = tour[bi + 1];
+        const int e_bi = D[size_t(a0) * n + a1];
+        int bj = n;
+        for (int m = 0; m < MB && bj == n; ++m) {
+            const int c = lane + 64 * m;
+            bool hit = false;
+            if (c >= bi + 2 && c < n && !(bi == 0 && c == n - 1)) {
+                const int xc = tour[c], xn = tour[c + 1 < n ? c + 1 : 0];
+                const int d = D[size_t(a0) * n + xc] + D[size_t(a1) * n + xn] - e_bi - D[size_t(xc) * n + xn];
+                hit = d == dbest;
+            }
+            const uint64_t bal = __ballot(hit);
+            if (bal) bj = 64 * m + __ffsll((unsigned long long)bal) - 1;
+        }
+        // reverse tour[bi+1 .. bj]
+        const int len = bj - bi;
+        for (int k = lane; k < len / 2; k += 64) {
+            const uint16_t t0 = tour[bi + 1 + k];
+            tour[bi + 1 + k] = tour[bj - k];
+            tour[bj - k] = t0;
+        }
+        compiler_fence();
+        F += dbest;
+        ++moves;
+        if (kp.ee_max_moves > 0 && moves >= kp.ee_max_moves) break;
+    }
+    for (int k = lane; k < n; k += 64) xg[k] = tour[k];
+    const bool better = F < st.FP[p];
+    if (better)
+        for (int k = lane; k < n; k += 64) st.P[size_t(p) * ns + k] = tour[k];
+    if (lane == 0) {
+        st.F[p] = F;
+        if (better) st.FP[p] = F;
+        atomicAdd(reinterpret_cast<unsigned long long *>(&h->n_sweeps), (unsigned long long)sweeps);
+        atomicAdd(reinterpret_cast<unsigned long long *>(&h->n_moves), (unsigned long long)moves);
+    }
+}
+
+template <int MB>
+hipError_t launch_wave(const int32_t *D, const View &st, const KParams &kp, hipStream_t s)
+{
+    const size_t lds = size_t(WaveCfg<MB>::BS) * 4 * 2 + size_t(st.ns) * 2;
+    const bool vec4 = (st.n & 3) == 0 && (reinterpret_cast<uintptr_t>(D) & 15) == 0;
+    hipError_t e = vec4 ? allow_lds(k_2opt_wave<MB, true>, lds) : allow_lds(k_2opt_wave<MB, false>, lds);
+    if (e != hipSuccess) return e;
+    if (vec4)
+        k_2opt_wave<MB, true><<<st.S, 64, lds, s>>>(D, st, kp);
+    else
+        k_2opt_wave<MB, false><<<st.S, 64, lds, s>>>(D, st, kp);
+    return hipGetLastError();
+}
+
 hipError_t launch_2opt(const int32_t *D, const View &st, const KParams &kp, hipStream_t s)
 {
+    if (st.n <= 64) return launch_wave<1>(D, st, kp, s);
+    if (st.n <= 128) return launch_wave<2>(D, st, kp, s);
+    if (st.n <= 256) return launch_wave<4>(D, st, kp, s);
+    if (st.n <= 512) return launch_wave<8>(D, st, kp, s);
+    if (st.n <= 1024) return launch_wave<16>(D, st, kp, s);
     const size_t lds = size_t(st.ns) * 2 + size_t(st.ns) * 4 * 4;
     hipError_t e = allow_lds(k_2opt_rows, lds);
     if (e != hipSuccess) return e;

@@ -52,21 +52,30 @@ def mismatches(gpu: dict, st: "oracle.State") -> list:
 
 
 def synthetic_state(D: np.ndarray, prm: dict, t: int, seed: int, max_vlen=None) -> "oracle.State":
-    """A mid-run swarm state at generation t: random tours, personal bests
-    and velocities (any list of transpositions is a velocity), costs from the
-    oracle, G the cheapest personal best. The trace is flat at F_G."""
+    """A mid-run swarm state at generation t: random tours, personal bests and
+    velocities, costs from the oracle, G the cheapest personal best. A
+    velocity is the canonical difference of two tours, as every velocity the
+    method produces is; some are short (a few exchanges apart), some long.
+    The trace is flat at F_G."""
     n, S = D.shape[0], prm["swarm_size"]
     rng = np.random.default_rng(seed)
     st = oracle.State(n, S, prm["max_generations"] + 1)
     for p in range(S):
         st.X[p] = rng.permutation(n)
         st.P[p] = rng.permutation(n) if p % 4 else st.X[p]
-        L = int(rng.integers(0, (max_vlen or n - 1) + 1)) if n > 1 else 0
-        if L:
-            a = rng.integers(0, n, size=L)
-            b = (a + rng.integers(1, n, size=L)) % n
-            st.V[p, :L, 0], st.V[p, :L, 1] = a, b
-        st.VL[p] = L
+        ref = rng.permutation(n)
+        if p % 3 == 0:
+            tgt = rng.permutation(n)
+        else:
+            tgt = ref.copy()
+            for _ in range(int(rng.integers(0, 6))):
+                i, j = rng.integers(0, n, size=2)
+                tgt[i], tgt[j] = tgt[j], tgt[i]
+        v = oracle.bss(ref, tgt)
+        if max_vlen is not None:
+            v = v[:max_vlen] if len(v) <= max_vlen else oracle.bss(ref, ref)
+        st.V[p, : len(v)] = v
+        st.VL[p] = len(v)
         st.F[p] = oracle.tour_cost(D, st.X[p])
         st.FP[p] = oracle.tour_cost(D, st.P[p])
         if st.FP[p] > st.F[p]:

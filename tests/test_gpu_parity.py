@@ -180,6 +180,28 @@ def test_collapsed_swarm_mutation(dp):
     assert not bad, bad
 
 
+def test_import_export_round_trip_and_rejection(dp):
+    n, S = 40, 24
+    D = oracle.build_dist(scenes.random_points(n, seed=8, n_boxes=2))
+    prm = scenes.swarm_params(S, 20, seed=4)
+    st = synthetic_state(D, prm, t=5, seed=21)
+    Dg = _dev(D)
+    state = dp.init_nn(Dg, prm)
+    note("import / export round trip")
+    dp.import_state(state, n, S, as_host(st))
+    assert not mismatches(dp.export_state(state, n, S), st)
+    bad = as_host(st)
+    bad["V"][2, :2] = [[5, 7], [7, 9]]      # moves label 7 again after placing it: not canonical
+    bad["vlen"][2] = 2
+    with pytest.raises(dp.DpsoError) as ei:
+        dp.import_state(state, n, S, bad)
+    assert ei.value.status == dp.E_INVAL
+    bad = as_host(st)
+    bad["X"][3, [0, 1]] = bad["X"][3, 0]             # not a permutation
+    with pytest.raises(dp.DpsoError):
+        dp.import_state(state, n, S, bad)
+
+
 def test_split_run_equals_single_run(dp):
     sc, prm = scenes.workload(1)
     D = oracle.build_dist(sc)
