@@ -122,8 +122,23 @@ __global__ __launch_bounds__(kThreads) void k_2opt_rows(const int32_t *__restric
 // is evaluated; rows alternate between two LDS buffers at a fixed stride so
 // the gathers use immediate offsets. A single wave owns its LDS: LDS operations
 // of one wave complete in order, and a compiler fence keeps program order.
+// Tuning knobs: rows of D in flight per wave (1 or 2), byte offsets of the
+// gather labels packed two per register, and the occupancy the register
+// allocation aims at (waves per SIMD).
+#ifndef DPSO_2OPT_PREFETCH
+#define DPSO_2OPT_PREFETCH 1
+#endif
+#ifndef DPSO_2OPT_PACK
+#define DPSO_2OPT_PACK 0
+#endif
+#ifndef DPSO_2OPT_WAVES
+#define DPSO_2OPT_WAVES 4
+#endif
+
 namespace {
 
+constexpr int kPrefetch = DPSO_2OPT_PREFETCH;
+constexpr bool kPack = DPSO_2OPT_PACK != 0;
 constexpr int kPad = 1 << 30;  // edge cost of padding columns: never the minimum
 constexpr int kNone = 0x7fffffff;
 
@@ -183,12 +198,33 @@ struct RowPipe {
 
 template <int MB, bool VEC4>
 struct SweepState {
-    int loff[MB];  // x_c+1 of each owned column (label = index into a row)
+    // byte offset (4 x_c+1) of each owned column in a row buffer; packed two
+    // per register when kPack
+    int loff[kPack ? (MB + 1) / 2 : MB];
     int ne[MB];    // -D[x_c][x_c+1], kPad for padding columns
     int g[MB];     // gathers of the previous row
-    RowPipe<MB, VEC4> pipe[2];  // rows x_i+1 and x_i+2 in flight (by row parity)
+    RowPipe<MB, VEC4> pipe[kPrefetch];  // rows in flight (alternating by row parity)
     int best, best_i;
+
+    __device__ inline int off(int m) const
+    {
+        if constexpr (kPack) return (m & 1) ? (loff[m >> 1] >> 16) : (loff[m >> 1] & 0xffff);
+        return loff[m];
+    }
+    __device__ inline void set_off(int m, int v)
+    {
+        if constexpr (kPack) {
+            loff[m >> 1] = (m & 1) ? ((loff[m >> 1] & 0xffff) | (v << 16)) : v;
+        } else {
+            loff[m] = v;
+        }
+    }
 };
+
+__device__ inline int lds_word(const int32_t *base, int byte_off)
+{
+    return *reinterpret_cast<const int32_t *>(reinterpret_cast<const char *>(base) + byte_off);
+}
 
 // Row i with the first active block M0 and buffer BI (0 for even rows).
 template <int MB, bool VEC4, int M0, int BI>
@@ -199,8 +235,9 @@ __device__ __forceinline__ void sweep_row(SweepState<MB, VEC4> &S, const int32_t
     int32_t *cur = bufs + BI * BS;
     const int32_t *prv = bufs + (1 - BI) * BS;
     const int lane = threadIdx.x;
-    S.pipe[BI].store(cur, n);                  // row of x_i+1, loaded two rows ago
-    if (i + 5 <= n) S.pipe[BI].load(D + size_t(tour[i + 3]) * n, n);  // for row i+2
+    constexpr int P = kPrefetch == 2 ? BI : 0;
+    S.pipe[P].store(cur, n);  // row of x_i+1, loaded kPrefetch rows ago
+    if (i + kPrefetch + 3 <= n) S.pipe[P].load(D + size_t(tour[i + 1 + kPrefetch]) * n, n);
     compiler_fence();
     const int ei = prv[tour[i + 1]];           // D[x_i][x_i+1]
     int carry = M0 > 0 ? rotate_up(S.g[M0 > 0 ? M0 - 1 : 0]) : 0;
@@ -210,7 +247,7 @@ __device__ __forceinline__ void sweep_row(SweepState<MB, VEC4> &S, const int32_t
         const int r = rotate_up(S.g[m]);
         const int a = lane == 0 ? carry : r;
         carry = r;
-        const int b = cur[S.loff[m]];
+        const int b = lds_word(cur, S.off(m));
         int d = a + b + S.ne[m];
         if (m == M0) d = lane + 64 * M0 < i + 2 ? kNone : d;
         rm = min(rm, d);
@@ -242,7 +279,7 @@ __device__ __forceinline__ void sweep_phase(SweepState<MB, VEC4> &S, const int32
 }  // namespace
 
 template <int MB, bool VEC4>
-__global__ __launch_bounds__(64) void k_2opt_wave(const int32_t *__restrict__ D, View st, KParams kp)
+__global__ __launch_bounds__(64, DPSO_2OPT_WAVES) void k_2opt_wave(const int32_t *__restrict__ D, View st, KParams kp)
 {
     constexpr int BS = WaveCfg<MB>::BS;
     Hdr *h = st.hdr;
@@ -265,10 +302,10 @@ __global__ __launch_bounds__(64) void k_2opt_wave(const int32_t *__restrict__ D,
             const int c = lane + 64 * m;
             if (c < n) {
                 const int a = tour[c], b = tour[c + 1 < n ? c + 1 : 0];
-                S.loff[m] = b;
+                S.set_off(m, 4 * b);
                 S.ne[m] = -D[size_t(a) * n + b];
             } else {
-                S.loff[m] = 0;
+                S.set_off(m, 0);
                 S.ne[m] = kPad;
             }
         }
@@ -277,9 +314,10 @@ __global__ __launch_bounds__(64) void k_2opt_wave(const int32_t *__restrict__ D,
         S.pipe[0].store(bufs + BS, n);
         compiler_fence();
 #pragma unroll
-        for (int m = 0; m < MB; ++m) S.g[m] = bufs[BS + S.loff[m]];
-        S.pipe[0].load(D + size_t(tour[1]) * n, n);
-        S.pipe[1].load(D + size_t(tour[2]) * n, n);
+        for (int m = 0; m < MB; ++m) S.g[m] = lds_word(bufs + BS, S.off(m));
+#pragma unroll
+        for (int k = 0; k < kPrefetch; ++k)
+            if (k + 1 < n) S.pipe[k].load(D + size_t(tour[k + 1]) * n, n);
         S.best = kNone;
         S.best_i = 0;
         sweep_phase<MB, VEC4, 0>(S, D, bufs, tour, n);
