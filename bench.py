@@ -20,6 +20,32 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_facade1000.md")
+KERNEL_SRC = os.path.join(ROOT, "paper_1706_04399_amd", "csrc", "twoopt.hip")
+
+
+def exchange_kernel_name(n: int) -> str:
+    for mb in (1, 2, 4, 8, 16):
+        if n <= 64 * mb:
+            return f"k_2opt_wave<{mb}, {'true' if n % 4 == 0 else 'false'}>"
+    return "k_2opt_rows"
+
+
+def hbm_traffic_per_launch():
+    """HBM bytes per edge-exchange launch from the committed rocprofv3 counter
+    summary, or None if the kernel source changed since it was taken."""
+    import hashlib
+    import re
+    try:
+        text = open(TRAFFIC_FILE).read()
+        src = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    except OSError:
+        return None
+    h = re.search(r"source_sha256_16:\s*([0-9a-f]{16})", text)
+    b = re.search(r"traffic_bytes_per_launch:\s*(\d+)", text)
+    if not h or not b or h.group(1) != src:
+        return None
+    return int(b.group(1))
 
 
 def cpu_baseline(seconds: float):
@@ -85,6 +111,8 @@ def main():
     launches = phases["exchange_launches"]
     avg_launch_s = phases["ms_exchange"] / launches / 1e3
     achieved = sweeps / launches * bytes_per_sweep / avg_launch_s / 1e9
+    tb = hbm_traffic_per_launch()
+    traffic = round(tb / avg_launch_s / 1e9, 2) if tb is not None else None
 
     line = {
         "metric": "particle-iters/s at n=1000",
@@ -97,9 +125,9 @@ def main():
         "config": {"workload": "facade n=1000, 20 boxes, swarm 4096, edge exchange every "
                                "generation", "n": n, "swarm": S, "generations": args.steps,
                    "parallelism": "none (1 GPU)"},
-        "roofline": {"bound": "hbm", "kernel": "k_2opt_rows",
+        "roofline": {"bound": "hbm", "kernel": exchange_kernel_name(n),
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic},
         "phases_ms": {k: round(v, 2) for k, v in phases.items() if k.startswith("ms_")},
         "best_cost_mm": info1["best_cost"],
     }
