@@ -70,6 +70,54 @@ def cpu_baseline(seconds: float):
                       f"edge exchange every generation), {dt:.1f} s"}
 
 
+def bench_batch(count: int, generations: int):
+    """Batched workload: `count` independent instances (n log-uniform in
+    [20, 500], facades and bridges by seed), swarm 256 each, edge exchange on
+    stall. Solves/s of the batched path (one captured graph per run) against
+    the plain path solving the same instances one at a time."""
+    import torch
+    from paper_1706_04399_amd import dpso, scenes
+
+    sc = [scenes.batch_instance(i) for i in range(count)]
+    prm = [scenes.swarm_params(256, generations, seed=0, instance=i) for i in range(count)]
+    Ds = [dpso.build_dist(s) for s in sc]
+    torch.cuda.synchronize()
+    # plain path
+    t0 = time.perf_counter()
+    plain = []
+    for D, p in zip(Ds, prm):
+        st = dpso.init_nn(D, p)
+        dpso.run(D, p, st, generations)
+        plain.append(st)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    plain_best = [dpso.get_best(st)[1] for st in plain]
+    del plain
+    # batched path
+    stream = torch.cuda.Stream()
+    b = dpso.Batch(list(zip(Ds, prm)), stream=stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.init().run(generations)
+    stream.synchronize()
+    t_batch = time.perf_counter() - t0
+    batch_best = [dpso.get_best(st, stream)[1] for st in b.states]
+    same = plain_best == batch_best
+    ns = [s.n for s in sc]
+    return {
+        "metric": "batched solves/s", "value": round(count / t_batch, 3), "unit": "solves/s",
+        "plain_value": round(count / t_plain, 3), "speedup_vs_plain": round(t_plain / t_batch, 3),
+        "seconds_batched": round(t_batch, 3), "seconds_plain": round(t_plain, 3),
+        "particle_iters_per_s": round(256 * generations * count / t_batch, 1),
+        "identical_results": same, "n_gpus": 1, "higher_is_better": True, "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": f"{count} instances, n log-uniform in [20, 500] (min {min(ns)}, "
+                               f"max {max(ns)}), facade/bridge by seed, swarm 256, "
+                               f"{generations} generations, edge exchange on stall",
+                   "instances": count, "generations": generations},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -77,11 +125,18 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--batch", type=int, default=0,
+                    help="run the batched workload with this many instances instead")
+    ap.add_argument("--batch-generations", type=int, default=500)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (each swarm runs "
               "on one GPU; see the multi-GPU design notes)", file=sys.stderr)
         sys.exit(2)
+
+    if args.batch:
+        print(json.dumps(bench_batch(args.batch, args.batch_generations)), flush=True)
+        return
 
     import torch
     from paper_1706_04399_amd import dpso, scenes

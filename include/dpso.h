@@ -51,6 +51,7 @@ typedef int32_t dpso_status;
 #define DPSO_MAX_N 4096      /* largest number of viewpoints                    */
 #define DPSO_MAX_SWARM 65536 /* largest swarm                                   */
 #define DPSO_MAX_GRAPH 16384 /* largest n + 8 * n_boxes (visibility-graph nodes)  */
+#define DPSO_MAX_BATCH 65536 /* largest number of instances in one batched call  */
 
 /* Edge-exchange trigger (pseudo code of Sect. 3.3: exchange when the global
  * best did not improve; ALWAYS runs it every generation). */
@@ -185,6 +186,35 @@ typedef struct {
 dpso_status dpso_run_profiled(const int32_t *d_dist, int32_t n, const dpso_params *params,
                               void *d_state, size_t state_bytes, int32_t generations,
                               dpso_phase_times *times, void *stream);
+
+/* One swarm of a batch: its own distance matrix, parameters and state. */
+typedef struct {
+    const int32_t *d_dist;  /* device int32 [n][n]                          */
+    int32_t n;
+    dpso_params params;
+    void *d_state;          /* dpso_state_bytes(n, swarm_size, max_generations) */
+    size_t state_bytes;
+} dpso_batch_item;
+
+/* Bytes of device workspace for the tables of a batch of `count` swarms. */
+size_t dpso_batch_work_bytes(int32_t count);
+
+/* dpso_init_nn for many independent swarms (instances of different n and
+ * swarm size) in one pass of batched launches. d_work (device,
+ * dpso_batch_work_bytes(count)) receives the batch tables. Synchronises
+ * `stream`. */
+dpso_status dpso_init_batch(const dpso_batch_item *items, int32_t count, void *d_work,
+                            size_t work_bytes, void *stream);
+
+/* dpso_run for many independent swarms: every generation is one launch per
+ * phase covering all instances' particles (one per edge-exchange class),
+ * so each kernel boundary synchronises the whole batch and the hardware
+ * scheduler balances instances of uneven size. On a non-null stream that is
+ * not already capturing, the whole run is captured into one hipGraph and
+ * launched once. Each instance's result is identical to dpso_run on it
+ * alone. Synchronises `stream`. */
+dpso_status dpso_run_batch(const dpso_batch_item *items, int32_t count, int32_t generations,
+                           void *d_work, size_t work_bytes, void *stream);
 
 /* Progress counters. Synchronises `stream`. */
 dpso_status dpso_get_info(const void *d_state, dpso_info *info, void *stream);

@@ -82,6 +82,16 @@ dpso::KParams kernel_params(const dpso_params *p)
 
 hipStream_t as_stream(void *s) { return static_cast<hipStream_t>(s); }
 
+dpso::Inst make_inst(const int32_t *d_dist, void *d_state, const dpso::Layout &L, const dpso_params *params)
+{
+    dpso::Inst I{};
+    I.D = d_dist;
+    I.st = dpso::make_view(d_state, L);
+    I.kp = kernel_params(params);
+    I.cap = L.cap;
+    return I;
+}
+
 // Reads the header of a state (synchronising the stream).
 dpso_status read_header(const void *d_state, dpso::Hdr *h, hipStream_t s)
 {
@@ -154,6 +164,121 @@ bool host_velocity_tours(const uint16_t *pairs, int len, int n, uint16_t *from, 
            std::equal(check.begin(), check.begin() + 2 * len, pairs);
 }
 
+// Device workspace of a batch: the descriptors of all instances with two
+// prefix tables (per particle, per instance), and for every edge-exchange
+// class the descriptors of its members with their particle prefix.
+struct BatchLayout {
+    size_t inst, first_items, first_inst, cls_inst[dpso::kExchangeClasses],
+        cls_first[dpso::kExchangeClasses], total;
+};
+
+BatchLayout batch_layout(int32_t count)
+{
+    BatchLayout B{};
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t at = o; o = dpso::align256(o + bytes); return at; };
+    B.inst = take(sizeof(dpso::Inst) * size_t(count));
+    B.first_items = take(4 * size_t(count + 1));
+    B.first_inst = take(4 * size_t(count + 1));
+    for (int c = 0; c < dpso::kExchangeClasses; ++c) {
+        B.cls_inst[c] = take(sizeof(dpso::Inst) * size_t(count));
+        B.cls_first[c] = take(4 * size_t(count + 1));
+    }
+    B.total = o;
+    return B;
+}
+
+struct BatchPlan {
+    dpso::Batch items, instances, cls[dpso::kExchangeClasses];
+    int total = 0, max_ns = 0, cls_total[dpso::kExchangeClasses] = {}, cls_max_ns[dpso::kExchangeClasses] = {};
+    bool any_mutation = false, any_exchange = false;
+};
+
+// Validates every item, writes the tables to the workspace (synchronising
+// the stream) and returns the launch plan.
+dpso_status plan_batch(const dpso_batch_item *items, int32_t count, void *d_work, size_t work_bytes,
+                       hipStream_t s, BatchPlan &plan)
+{
+    if (!items || !d_work) return fail(DPSO_E_INVAL, "items and d_work must be non-NULL");
+    if (count < 1 || count > DPSO_MAX_BATCH)
+        return fail(DPSO_E_INVAL, "batch of %d instances outside 1..%d", count, DPSO_MAX_BATCH);
+    const BatchLayout BL = batch_layout(count);
+    if (work_bytes < BL.total) return fail(DPSO_E_NOMEM, "workspace of %zu bytes, %zu needed", work_bytes, BL.total);
+    std::vector<unsigned char> host(BL.total, 0);
+    auto inst = reinterpret_cast<dpso::Inst *>(host.data() + BL.inst);
+    auto first_items = reinterpret_cast<int32_t *>(host.data() + BL.first_items);
+    auto first_inst = reinterpret_cast<int32_t *>(host.data() + BL.first_inst);
+    int64_t total = 0;
+    int cls_count[dpso::kExchangeClasses] = {};
+    for (int32_t i = 0; i < count; ++i) {
+        const dpso_batch_item &it = items[i];
+        dpso_status st = check_params(&it.params, it.n);
+        if (st) {
+            char why[sizeof g_error];
+            strncpy(why, g_error, sizeof why);
+            why[sizeof why - 1] = 0;
+            return fail(st, "item %d: %s", i, why);
+        }
+        if (!it.d_dist || !it.d_state) return fail(DPSO_E_INVAL, "item %d: d_dist and d_state must be non-NULL", i);
+        const dpso::Layout L = dpso::make_layout(it.n, it.params.swarm_size, it.params.max_generations + 1);
+        if (it.state_bytes < L.total)
+            return fail(DPSO_E_NOMEM, "item %d: state buffer of %zu bytes, %zu needed", i, it.state_bytes, L.total);
+        inst[i] = make_inst(it.d_dist, it.d_state, L, &it.params);
+        first_items[i] = int32_t(total);
+        first_inst[i] = i;
+        total += it.params.swarm_size;
+        plan.max_ns = std::max(plan.max_ns, L.ns);
+        plan.any_mutation |= it.params.mutation_period > 0;
+        const int c = dpso::exchange_class(it.n, it.d_dist);
+        if (it.params.ee_trigger != DPSO_EE_OFF) {
+            plan.any_exchange = true;
+            auto ci = reinterpret_cast<dpso::Inst *>(host.data() + BL.cls_inst[c]);
+            auto cf = reinterpret_cast<int32_t *>(host.data() + BL.cls_first[c]);
+            ci[cls_count[c]] = inst[i];
+            cf[cls_count[c]] = plan.cls_total[c];
+            cls_count[c] += 1;
+            plan.cls_total[c] += it.params.swarm_size;
+            plan.cls_max_ns[c] = std::max(plan.cls_max_ns[c], L.ns);
+        }
+    }
+    if (total > (int64_t(1) << 30)) return fail(DPSO_E_RANGE, "batch holds %lld particles", (long long)total);
+    first_items[count] = int32_t(total);
+    first_inst[count] = count;
+    unsigned char *dev = static_cast<unsigned char *>(d_work);
+    plan.total = int(total);
+    plan.items = dpso::Batch{reinterpret_cast<const dpso::Inst *>(dev + BL.inst),
+                             reinterpret_cast<const int32_t *>(dev + BL.first_items), count};
+    plan.instances = dpso::Batch{reinterpret_cast<const dpso::Inst *>(dev + BL.inst),
+                                 reinterpret_cast<const int32_t *>(dev + BL.first_inst), count};
+    for (int c = 0; c < dpso::kExchangeClasses; ++c) {
+        reinterpret_cast<int32_t *>(host.data() + BL.cls_first[c])[cls_count[c]] = plan.cls_total[c];
+        plan.cls[c] = dpso::Batch{reinterpret_cast<const dpso::Inst *>(dev + BL.cls_inst[c]),
+                                  reinterpret_cast<const int32_t *>(dev + BL.cls_first[c]), cls_count[c]};
+    }
+    HIP_TRY(hipMemcpyAsync(d_work, host.data(), host.size(), hipMemcpyHostToDevice, s), "copy batch tables");
+    HIP_TRY(hipStreamSynchronize(s), "synchronise stream");
+    return DPSO_OK;
+}
+
+// All launches of `generations` generations of a batch.
+hipError_t enqueue_batch(const BatchPlan &P, int32_t generations, hipStream_t s)
+{
+    hipError_t e = dpso::launch_batch_check(P.items, P.instances, P.total, P.max_ns, s);
+    for (int32_t g = 0; g < generations && e == hipSuccess; ++g) {
+        e = dpso::launch_batch_move(P.items, P.instances, P.total, P.max_ns, s);
+        if (e == hipSuccess && P.any_mutation)
+            e = dpso::launch_batch_mutation(P.items, P.instances, P.total, P.max_ns, s);
+        if (e == hipSuccess) e = dpso::launch_batch_gbest(P.items, P.instances, P.total, P.max_ns, 1, s);
+        if (P.any_exchange) {
+            for (int c = 0; c < dpso::kExchangeClasses && e == hipSuccess; ++c)
+                if (P.cls[c].count > 0) e = dpso::launch_batch_2opt(c, P.cls[c], P.cls_total[c], P.cls_max_ns[c], s);
+            if (e == hipSuccess) e = dpso::launch_batch_gbest(P.items, P.instances, P.total, P.max_ns, 2, s);
+        }
+        if (e == hipSuccess) e = dpso::launch_batch_end(P.items, P.instances, P.total, P.max_ns, s);
+    }
+    return e;
+}
+
 // Event pool for dpso_run_profiled, reused across calls.
 std::mutex g_event_mutex;
 std::vector<hipEvent_t> g_events;
@@ -180,28 +305,28 @@ dpso_status run_impl(const int32_t *d_dist, int32_t n, const dpso_params *params
     const dpso::Layout L = dpso::make_layout(n, params->swarm_size, params->max_generations + 1);
     if (state_bytes < L.total)
         return fail(DPSO_E_NOMEM, "state buffer of %zu bytes, %zu needed", state_bytes, L.total);
-    const dpso::View v = dpso::make_view(d_state, L);
-    const dpso::KParams kp = kernel_params(params);
+    const dpso::Inst I = make_inst(d_dist, d_state, L, params);
+    const dpso::KParams &kp = I.kp;
     hipStream_t s = as_stream(stream);
     std::vector<hipEvent_t> ev;
     constexpr int kMarks = 6;  // after move, mutation, gbest, exchange, gbest, end
     if (times && (st = events(size_t(generations) * kMarks + 1, ev))) return st;
     size_t mark = 0;
     auto stamp = [&]() -> hipError_t { return times ? hipEventRecord(ev[mark++], s) : hipSuccess; };
-    HIP_TRY(dpso::launch_check(v, L.cap, s), "launch check");
+    HIP_TRY(dpso::launch_check(I, s), "launch check");
     HIP_TRY(stamp(), "record event");
     for (int32_t g = 0; g < generations; ++g) {
-        HIP_TRY(dpso::launch_move(d_dist, v, kp, s), "launch move");
+        HIP_TRY(dpso::launch_move(I, s), "launch move");
         HIP_TRY(stamp(), "record event");
-        if (kp.mutation_period > 0) HIP_TRY(dpso::launch_mutation(d_dist, v, kp, s), "launch mutation");
+        if (kp.mutation_period > 0) HIP_TRY(dpso::launch_mutation(I, s), "launch mutation");
         HIP_TRY(stamp(), "record event");
-        HIP_TRY(dpso::launch_gbest(v, kp, 1, s), "launch gbest");
+        HIP_TRY(dpso::launch_gbest(I, 1, s), "launch gbest");
         HIP_TRY(stamp(), "record event");
-        if (kp.ee_trigger != DPSO_EE_OFF) HIP_TRY(dpso::launch_2opt(d_dist, v, kp, s), "launch 2-opt");
+        if (kp.ee_trigger != DPSO_EE_OFF) HIP_TRY(dpso::launch_2opt(I, s), "launch 2-opt");
         HIP_TRY(stamp(), "record event");
-        if (kp.ee_trigger != DPSO_EE_OFF) HIP_TRY(dpso::launch_gbest(v, kp, 2, s), "launch gbest");
+        if (kp.ee_trigger != DPSO_EE_OFF) HIP_TRY(dpso::launch_gbest(I, 2, s), "launch gbest");
         HIP_TRY(stamp(), "record event");
-        HIP_TRY(dpso::launch_end(v, kp, s), "launch end");
+        HIP_TRY(dpso::launch_end(I, s), "launch end");
         HIP_TRY(stamp(), "record event");
     }
     if (times) {
@@ -297,8 +422,8 @@ dpso_status dpso_init_nn(const int32_t *d_dist, int32_t n, const dpso_params *pa
     const dpso::Layout L = dpso::make_layout(n, params->swarm_size, params->max_generations + 1);
     if (state_bytes < L.total)
         return fail(DPSO_E_NOMEM, "state buffer of %zu bytes, %zu needed", state_bytes, L.total);
-    const dpso::View v = dpso::make_view(d_state, L);
-    HIP_TRY(dpso::launch_init(d_dist, v, kernel_params(params), L.cap, as_stream(stream)), "launch init");
+    const dpso::Inst I = make_inst(d_dist, d_state, L, params);
+    HIP_TRY(dpso::launch_init(I, as_stream(stream)), "launch init");
     return ok();
 }
 
@@ -462,6 +587,58 @@ dpso_status dpso_import_state(void *d_state, size_t state_bytes, int32_t n, int3
     h.ee_ran = 0;
     HIP_TRY(hipMemcpyAsync(d_state, &h, sizeof h, hipMemcpyHostToDevice, s), "write header");
     HIP_TRY(hipStreamSynchronize(s), "synchronise stream");
+    return ok();
+}
+
+
+// ------------------------------------------------------------------ batches
+
+size_t dpso_batch_work_bytes(int32_t count)
+{
+    if (count < 1 || count > DPSO_MAX_BATCH) return 0;
+    return batch_layout(count).total;
+}
+
+dpso_status dpso_init_batch(const dpso_batch_item *items, int32_t count, void *d_work, size_t work_bytes,
+                            void *stream)
+{
+    BatchPlan plan;
+    dpso_status st = plan_batch(items, count, d_work, work_bytes, as_stream(stream), plan);
+    if (st) return st;
+    hipStream_t s = as_stream(stream);
+    HIP_TRY(dpso::launch_batch_init(plan.items, plan.instances, plan.total, plan.max_ns, s), "launch init");
+    HIP_TRY(hipStreamSynchronize(s), "synchronise stream");
+    return ok();
+}
+
+dpso_status dpso_run_batch(const dpso_batch_item *items, int32_t count, int32_t generations, void *d_work,
+                           size_t work_bytes, void *stream)
+{
+    if (generations < 0) return fail(DPSO_E_INVAL, "generations must be >= 0");
+    BatchPlan plan;
+    dpso_status st = plan_batch(items, count, d_work, work_bytes, as_stream(stream), plan);
+    if (st) return st;
+    hipStream_t s = as_stream(stream);
+    // the whole run as one graph when the stream can be captured
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    const bool graph = s != nullptr && hipStreamIsCapturing(s, &cap) == hipSuccess &&
+                       cap == hipStreamCaptureStatusNone && generations > 0;
+    if (graph) HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "begin capture");
+    hipError_t e = enqueue_batch(plan, generations, s);
+    if (graph) {
+        hipGraph_t g = nullptr;
+        const hipError_t ec = hipStreamEndCapture(s, &g);
+        if (e == hipSuccess) e = ec;
+        hipGraphExec_t x = nullptr;
+        if (e == hipSuccess) e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+        if (e == hipSuccess) e = hipGraphLaunch(x, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (x) hipGraphExecDestroy(x);
+        if (g) hipGraphDestroy(g);
+    } else if (e == hipSuccess) {
+        e = hipStreamSynchronize(s);
+    }
+    if (e != hipSuccess) return hip_fail(e, "batched run");
     return ok();
 }
 

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "state.hpp"
+
 namespace dpso {
 
 enum Purpose : uint64_t { kInit = 0, kVel = 1, kMut = 2 };
@@ -110,6 +112,22 @@ __device__ inline int64_t block_tour_cost(const int32_t *__restrict__ D, int n,
         s += D[size_t(a) * n + b];
     }
     return block_sum_i64(s, red);
+}
+
+// Instance and local index of block b in a batched launch (binary search
+// over the prefix table; uniform across the workgroup).
+__device__ inline const Inst &batch_pick(const Batch &B, int b, int &local)
+{
+    int lo = 0, hi = B.count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (B.first[mid] <= b)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    local = b - B.first[lo];
+    return B.inst[lo];
 }
 
 // Lets `kernel` take `bytes` of dynamic LDS (gfx950 has 160 KiB per CU).

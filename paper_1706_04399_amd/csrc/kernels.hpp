@@ -1,4 +1,4 @@
-// Host-side launchers of the device kernels (one translation unit each).
+// Host-side launchers of the device kernels.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -7,16 +7,31 @@
 
 namespace dpso {
 
-// swarm.hip
-hipError_t launch_init(const int32_t *D, const View &st, const KParams &kp, int32_t cap, hipStream_t s);
-hipError_t launch_check(const View &st, int32_t cap, hipStream_t s);
-hipError_t launch_move(const int32_t *D, const View &st, const KParams &kp, hipStream_t s);
-hipError_t launch_mutation(const int32_t *D, const View &st, const KParams &kp, hipStream_t s);
-hipError_t launch_gbest(const View &st, const KParams &kp, int mode, hipStream_t s);
-hipError_t launch_end(const View &st, const KParams &kp, hipStream_t s);
+// swarm.hip: one instance (descriptor by value)
+hipError_t launch_init(const Inst &I, hipStream_t s);
+hipError_t launch_check(const Inst &I, hipStream_t s);
+hipError_t launch_move(const Inst &I, hipStream_t s);
+hipError_t launch_mutation(const Inst &I, hipStream_t s);
+hipError_t launch_gbest(const Inst &I, int mode, hipStream_t s);
+hipError_t launch_end(const Inst &I, hipStream_t s);
 
-// twoopt.hip
-hipError_t launch_2opt(const int32_t *D, const View &st, const KParams &kp, hipStream_t s);
+// swarm.hip: many instances. `items` has one block per particle (total
+// blocks), `instances` one block per instance; max_ns sizes dynamic LDS.
+hipError_t launch_batch_init(const Batch &items, const Batch &instances, int total, int max_ns, hipStream_t s);
+hipError_t launch_batch_check(const Batch &items, const Batch &instances, int total, int max_ns, hipStream_t s);
+hipError_t launch_batch_move(const Batch &items, const Batch &instances, int total, int max_ns, hipStream_t s);
+hipError_t launch_batch_mutation(const Batch &items, const Batch &instances, int total, int max_ns,
+                                 hipStream_t s);
+hipError_t launch_batch_gbest(const Batch &items, const Batch &instances, int total, int max_ns, int mode,
+                              hipStream_t s);
+hipError_t launch_batch_end(const Batch &items, const Batch &instances, int total, int max_ns, hipStream_t s);
+
+// twoopt.hip: the edge-exchange kernel depends on n (columns held per lane)
+// and on the alignment of D; instances of one class share a launch.
+constexpr int kExchangeClasses = 11;
+int exchange_class(int n, const int32_t *D);
+hipError_t launch_2opt(const Inst &I, hipStream_t s);
+hipError_t launch_batch_2opt(int cls, const Batch &items, int total, int max_ns, hipStream_t s);
 
 // dist.hip
 size_t dist_work_bytes(int32_t n, int32_t n_boxes);

@@ -101,4 +101,21 @@ struct KParams {
     int32_t det_count;  // number of nearest-neighbour seeded particles
 };
 
+// One swarm as the kernels see it: its distance matrix, state and params.
+struct Inst {
+    const int32_t *D;
+    View st;
+    KParams kp;
+    int32_t cap;  // trace capacity (max_generations + 1)
+    int32_t pad;
+};
+
+// Many swarms in one launch: block b belongs to the instance i with
+// first[i] <= b < first[i + 1] and handles item b - first[i] of it.
+struct Batch {
+    const Inst *inst;
+    const int32_t *first;  // [count + 1]
+    int32_t count;
+};
+
 }  // namespace dpso

@@ -22,12 +22,14 @@ namespace {
 constexpr int kThreads = 256;
 }
 
-__global__ __launch_bounds__(kThreads) void k_2opt_rows(const int32_t *__restrict__ D, View st,
-                                                        KParams kp)
+__device__ __forceinline__ void twoopt_rows_body(const Inst &I, int p)
 {
+    const int32_t *__restrict__ D = I.D;
+    const View st = I.st;
+    const KParams kp = I.kp;
     Hdr *h = st.hdr;
     if (h->err || h->done || !h->ee_ran) return;
-    const int p = blockIdx.x, n = st.n, ns = st.ns, tid = threadIdx.x;
+    const int n = st.n, ns = st.ns, tid = threadIdx.x;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ uint64_t red[kThreads / 64];
     uint16_t *x = reinterpret_cast<uint16_t *>(smem);
@@ -279,12 +281,15 @@ __device__ __forceinline__ void sweep_phase(SweepState<MB, VEC4> &S, const int32
 }  // namespace
 
 template <int MB, bool VEC4>
-__global__ __launch_bounds__(64, DPSO_2OPT_WAVES) void k_2opt_wave(const int32_t *__restrict__ D, View st, KParams kp)
+__device__ __forceinline__ void twoopt_wave_body(const Inst &I, int p)
 {
     constexpr int BS = WaveCfg<MB>::BS;
+    const int32_t *__restrict__ D = I.D;
+    const View st = I.st;
+    const KParams kp = I.kp;
     Hdr *h = st.hdr;
     if (h->err || h->done || !h->ee_ran) return;
-    const int p = blockIdx.x, n = st.n, ns = st.ns, lane = threadIdx.x;
+    const int n = st.n, ns = st.ns, lane = threadIdx.x;
     extern __shared__ __align__(16) unsigned char smem[];
     int32_t *bufs = reinterpret_cast<int32_t *>(smem);  // [2][BS]
     uint16_t *tour = reinterpret_cast<uint16_t *>(bufs + 2 * BS);
@@ -366,32 +371,93 @@ __global__ __launch_bounds__(64, DPSO_2OPT_WAVES) void k_2opt_wave(const int32_t
     }
 }
 
-template <int MB>
-hipError_t launch_wave(const int32_t *D, const View &st, const KParams &kp, hipStream_t s)
+template <int MB, bool VEC4>
+__global__ __launch_bounds__(64, DPSO_2OPT_WAVES) void k_2opt_wave(Inst I)
 {
-    const size_t lds = size_t(WaveCfg<MB>::BS) * 4 * 2 + size_t(st.ns) * 2;
-    const bool vec4 = (st.n & 3) == 0 && (reinterpret_cast<uintptr_t>(D) & 15) == 0;
-    hipError_t e = vec4 ? allow_lds(k_2opt_wave<MB, true>, lds) : allow_lds(k_2opt_wave<MB, false>, lds);
-    if (e != hipSuccess) return e;
-    if (vec4)
-        k_2opt_wave<MB, true><<<st.S, 64, lds, s>>>(D, st, kp);
+    twoopt_wave_body<MB, VEC4>(I, int(blockIdx.x));
+}
+
+template <int MB, bool VEC4>
+__global__ __launch_bounds__(64, DPSO_2OPT_WAVES) void k_2opt_wave_batch(Batch B)
+{
+    int p;
+    const Inst &I = batch_pick(B, int(blockIdx.x), p);
+    twoopt_wave_body<MB, VEC4>(I, p);
+}
+
+__global__ __launch_bounds__(kThreads) void k_2opt_rows(Inst I) { twoopt_rows_body(I, int(blockIdx.x)); }
+
+__global__ __launch_bounds__(kThreads) void k_2opt_rows_batch(Batch B)
+{
+    int p;
+    const Inst &I = batch_pick(B, int(blockIdx.x), p);
+    twoopt_rows_body(I, p);
+}
+
+namespace {
+
+template <int MB, bool VEC4>
+hipError_t launch_wave(const Inst *one, const Batch &B, int grid, int max_ns, hipStream_t s)
+{
+    const size_t lds = size_t(WaveCfg<MB>::BS) * 4 * 2 + size_t(max_ns) * 2;
+    hipError_t e = allow_lds(k_2opt_wave<MB, VEC4>, lds);
+    if (e == hipSuccess) e = allow_lds(k_2opt_wave_batch<MB, VEC4>, lds);
+    if (e != hipSuccess || grid <= 0) return e;
+    if (one)
+        k_2opt_wave<MB, VEC4><<<grid, 64, lds, s>>>(*one);
     else
-        k_2opt_wave<MB, false><<<st.S, 64, lds, s>>>(D, st, kp);
+        k_2opt_wave_batch<MB, VEC4><<<grid, 64, lds, s>>>(B);
     return hipGetLastError();
 }
 
-hipError_t launch_2opt(const int32_t *D, const View &st, const KParams &kp, hipStream_t s)
+hipError_t launch_rows(const Inst *one, const Batch &B, int grid, int max_ns, hipStream_t s)
 {
-    if (st.n <= 64) return launch_wave<1>(D, st, kp, s);
-    if (st.n <= 128) return launch_wave<2>(D, st, kp, s);
-    if (st.n <= 256) return launch_wave<4>(D, st, kp, s);
-    if (st.n <= 512) return launch_wave<8>(D, st, kp, s);
-    if (st.n <= 1024) return launch_wave<16>(D, st, kp, s);
-    const size_t lds = size_t(st.ns) * 2 + size_t(st.ns) * 4 * 4;
+    const size_t lds = size_t(max_ns) * 2 + size_t(max_ns) * 4 * 4;
     hipError_t e = allow_lds(k_2opt_rows, lds);
-    if (e != hipSuccess) return e;
-    k_2opt_rows<<<st.S, kThreads, lds, s>>>(D, st, kp);
+    if (e == hipSuccess) e = allow_lds(k_2opt_rows_batch, lds);
+    if (e != hipSuccess || grid <= 0) return e;
+    if (one)
+        k_2opt_rows<<<grid, kThreads, lds, s>>>(*one);
+    else
+        k_2opt_rows_batch<<<grid, kThreads, lds, s>>>(B);
     return hipGetLastError();
+}
+
+hipError_t launch_class(int cls, const Inst *one, const Batch &B, int grid, int max_ns, hipStream_t s)
+{
+    switch (cls) {
+    case 0: return launch_wave<1, true>(one, B, grid, max_ns, s);
+    case 1: return launch_wave<2, true>(one, B, grid, max_ns, s);
+    case 2: return launch_wave<4, true>(one, B, grid, max_ns, s);
+    case 3: return launch_wave<8, true>(one, B, grid, max_ns, s);
+    case 4: return launch_wave<16, true>(one, B, grid, max_ns, s);
+    case 5: return launch_wave<1, false>(one, B, grid, max_ns, s);
+    case 6: return launch_wave<2, false>(one, B, grid, max_ns, s);
+    case 7: return launch_wave<4, false>(one, B, grid, max_ns, s);
+    case 8: return launch_wave<8, false>(one, B, grid, max_ns, s);
+    case 9: return launch_wave<16, false>(one, B, grid, max_ns, s);
+    default: return launch_rows(one, B, grid, max_ns, s);
+    }
+}
+
+}  // namespace
+
+int exchange_class(int n, const int32_t *D)
+{
+    if (n > 1024) return kExchangeClasses - 1;
+    const bool vec4 = (n & 3) == 0 && (reinterpret_cast<uintptr_t>(D) & 15) == 0;
+    const int mb = n <= 64 ? 0 : n <= 128 ? 1 : n <= 256 ? 2 : n <= 512 ? 3 : 4;
+    return vec4 ? mb : 5 + mb;
+}
+
+hipError_t launch_2opt(const Inst &I, hipStream_t s)
+{
+    return launch_class(exchange_class(I.st.n, I.D), &I, Batch{}, I.st.S, I.st.ns, s);
+}
+
+hipError_t launch_batch_2opt(int cls, const Batch &items, int total, int max_ns, hipStream_t s)
+{
+    return launch_class(cls, nullptr, items, total, max_ns, s);
 }
 
 }  // namespace dpso

@@ -54,6 +54,11 @@ class PhaseTimes(C.Structure):
                 ("generations", C.c_int32), ("exchange_launches", C.c_int32)]
 
 
+class BatchItem(C.Structure):
+    _fields_ = [("d_dist", C.c_void_p), ("n", C.c_int32), ("params", Params),
+                ("d_state", C.c_void_p), ("state_bytes", C.c_size_t)]
+
+
 class HostState(C.Structure):
     _fields_ = [("X", C.c_void_p), ("P", C.c_void_p), ("V", C.c_void_p), ("vlen", C.c_void_p),
                 ("F", C.c_void_p), ("FP", C.c_void_p), ("G", C.c_void_p), ("trace", C.c_void_p),
@@ -74,6 +79,10 @@ EXPORTS = {
                              C.c_int32, C.c_void_p]),
     "dpso_run_profiled": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_size_t,
                                       C.c_int32, C.c_void_p, C.c_void_p]),
+    "dpso_batch_work_bytes": (C.c_size_t, [C.c_int32]),
+    "dpso_init_batch": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p]),
+    "dpso_run_batch": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_size_t,
+                                   C.c_void_p]),
     "dpso_get_info": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "dpso_get_best": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                   C.c_void_p]),
@@ -232,6 +241,42 @@ def import_state(state: torch.Tensor, n: int, swarm_size: int, host: dict, strea
                    int(host["best_cost"]))
     _check(lib().dpso_import_state(_dev(state, torch.uint8), state.numel(), n, swarm_size,
                                    C.byref(hs), _stream(stream)))
+
+
+def batch_work_bytes(count: int) -> int:
+    return int(lib().dpso_batch_work_bytes(count))
+
+
+class Batch:
+    """Many independent swarms driven by batched launches.
+
+    members: list of (D tensor, params dict); states are allocated here."""
+
+    def __init__(self, members, stream=None):
+        self.stream = stream
+        self.members = [(D, dict(p)) for D, p in members]
+        dev = self.members[0][0].device
+        self.states = [new_state(D.shape[0], p, dev) for D, p in self.members]
+        n = len(self.members)
+        self.work = torch.empty(max(batch_work_bytes(n), 1), dtype=torch.uint8, device=dev)
+        self.items = (BatchItem * n)()
+        for i, ((D, p), st) in enumerate(zip(self.members, self.states)):
+            self.items[i] = BatchItem(_dev(D, torch.int32).value, D.shape[0], _params(p),
+                                      _dev(st, torch.uint8).value, st.numel())
+
+    def init(self):
+        _check(lib().dpso_init_batch(self.items, len(self.members), C.c_void_p(self.work.data_ptr()),
+                                     self.work.numel(), _stream(self.stream)))
+        return self
+
+    def run(self, generations: int):
+        _check(lib().dpso_run_batch(self.items, len(self.members), int(generations),
+                                    C.c_void_p(self.work.data_ptr()), self.work.numel(),
+                                    _stream(self.stream)))
+        return self
+
+    def best(self, i: int):
+        return get_best(self.states[i], self.stream)
 
 
 class Solver:

@@ -230,3 +230,40 @@ def test_state_mismatch_is_reported(dp):
     with pytest.raises(dp.DpsoError) as ei:
         dp.get_info(state)
     assert ei.value.status == dp.E_STATE
+
+
+BATCH = [
+    # (n, swarm, overrides): every edge-exchange class, aligned and unaligned n
+    (1, 2, {}), (3, 5, {}), (30, 16, {}), (64, 8, dict(ee_trigger=2)), (65, 12, {}),
+    (127, 9, dict(mutation_period=0)), (128, 6, dict(ee_trigger=2, ee_max_moves=0)),
+    (200, 20, {}), (257, 7, dict(ee_trigger=2)), (515, 6, dict(ee_trigger=2)),
+    (1000, 5, dict(ee_trigger=2)), (1030, 3, dict(ee_trigger=2)),
+    (50, 10, dict(stall_limit=2)), (40, 10, dict(ee_trigger=0)),
+]
+
+
+def _batch_case(gens):
+    members = []
+    for k, (n, S, kw) in enumerate(BATCH):
+        sc = scenes.random_points(n, seed=100 + k, n_boxes=2 if n > 3 else 0)
+        D = oracle.build_dist(sc)
+        prm = scenes.swarm_params(S, gens if k != 0 else 5, seed=k, instance=k, **kw)
+        members.append((D, prm))
+    return members
+
+
+@pytest.mark.parametrize("graph", [False, True], ids=["launches", "graph"])
+def test_batch_matches_oracle(dp, graph):
+    import torch
+    gens = 9
+    members = _batch_case(gens)
+    stream = torch.cuda.Stream() if graph else None   # the null stream is never captured
+    note(f"batch of {len(members)} instances, graph={graph}")
+    b = dp.Batch([(_dev(D), p) for D, p in members], stream=stream).init()
+    b.run(4)
+    b.run(gens - 4)
+    for k, ((D, prm), st) in enumerate(zip(members, b.states)):
+        ref = oracle.new_state(D, prm)
+        oracle.run(D, prm, ref, gens)
+        bad = mismatches(dp.export_state(st, D.shape[0], prm["swarm_size"], stream), ref)
+        assert not bad, f"instance {k} (n={D.shape[0]}): {bad}"

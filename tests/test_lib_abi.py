@@ -104,3 +104,16 @@ def test_build_dist_validation(dp):
 def test_library_does_not_link_the_oracle(dp):
     data = open(dp._LIB_PATH, "rb").read()
     assert b"liboracle" not in data and b"or_build_dist" not in data
+
+
+def test_batch_validation(dp):
+    L = dp.lib()
+    assert dp.batch_work_bytes(0) == 0 and dp.batch_work_bytes(4) > 0
+    items = (dp.BatchItem * 2)()
+    fake = C.c_void_p(0x1000)
+    assert L.dpso_run_batch(items, 0, 1, fake, 1 << 20, None) == dp.E_INVAL
+    assert L.dpso_run_batch(items, 2, 1, fake, 16, None) == dp.E_NOMEM
+    need = dp.batch_work_bytes(2)
+    # items with zero swarm size are rejected before any device work
+    assert L.dpso_run_batch(items, 2, 1, fake, need, None) == dp.E_INVAL
+    assert L.dpso_run_batch(items, 2, -1, fake, need, None) == dp.E_INVAL
