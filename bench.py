@@ -118,6 +118,37 @@ def bench_batch(count: int, generations: int):
     }
 
 
+def bench_serve(count: int, rate: float, warmup: int, budget_mb: int, plain: bool):
+    """Served re-planning: Poisson arrivals at `rate`/s, n log-uniform in
+    [50, 800], swarm 512, 300 generations each; requests admitted first come,
+    first served under a device-memory budget and run as batches. With
+    `plain`, the same stream is served one request at a time on the
+    single-instance path (the baseline)."""
+    import torch
+    from paper_1706_04399_amd import serve
+
+    reqs = serve.poisson_requests(count, rate)
+    ex = serve.GpuExecutor(batched=not plain)
+    sched = serve.Scheduler(budget_mb << 20, ex.footprint, max_batch=1 if plain else 1024)
+    ex.solve(reqs[:2])                       # load kernels and warm the allocator
+    ex.cache.clear()
+    torch.cuda.synchronize()
+    recs = serve.serve(reqs, ex, sched)
+    s = serve.summary(recs, warmup=warmup)
+    return {
+        "metric": "served re-planning p99 latency" if not plain else "served re-planning p99 latency (one at a time)",
+        "value": round(s["p99_ms"], 2), "unit": "ms", "p50_ms": round(s["p50_ms"], 2),
+        "mean_ms": round(s["mean_ms"], 2), "max_ms": round(s["max_ms"], 2),
+        "solves_per_s": round(s["solves_per_s"], 2), "batches": s["batches"],
+        "mean_batch": round(s["mean_batch"], 2), "higher_is_better": False, "n_gpus": 1,
+        "dtype": "int32", "data": "synthetic",
+        "config": {"workload": f"Poisson arrivals at {rate}/s, n log-uniform in [50, 800], swarm 512, "
+                               f"300 generations, edge exchange on stall, {count} requests "
+                               f"(first {warmup} not counted), budget {budget_mb} MiB",
+                   "server": "one request at a time" if plain else "batched, FCFS admission"},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -128,6 +159,12 @@ def main():
     ap.add_argument("--batch", type=int, default=0,
                     help="run the batched workload with this many instances instead")
     ap.add_argument("--batch-generations", type=int, default=500)
+    ap.add_argument("--serve", type=int, default=0,
+                    help="serve this many re-planning requests instead")
+    ap.add_argument("--rate", type=float, default=50.0)
+    ap.add_argument("--serve-warmup", type=int, default=200)
+    ap.add_argument("--budget-mb", type=int, default=2048)
+    ap.add_argument("--plain", action="store_true", help="serve one request at a time")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (each swarm runs "
@@ -136,6 +173,10 @@ def main():
 
     if args.batch:
         print(json.dumps(bench_batch(args.batch, args.batch_generations)), flush=True)
+        return
+    if args.serve:
+        print(json.dumps(bench_serve(args.serve, args.rate, min(args.serve_warmup, args.serve // 4),
+                                     args.budget_mb, args.plain)), flush=True)
         return
 
     import torch

@@ -151,17 +151,32 @@ __device__ inline int rotate_up(int v)  // lane l receives lane l-1 (lane 0: lan
 
 __device__ inline void compiler_fence() { __asm__ __volatile__("" ::: "memory"); }
 
-template <int MB>
+// Row buffers: two per wave, each BS ints. Rows that do not start on 16
+// bytes spill up to 3 ints before and after a buffer, so those kernels keep
+// guard words around each buffer; aligned kernels keep none (10 KiB of LDS
+// per wave at MB = 16: 16 waves per CU).
+template <int MB, bool VEC4>
 struct WaveCfg {
-    static constexpr int RV = (MB + 3) / 4;  // int4 per lane per row
-    static constexpr int BS = 256 * RV;      // row buffer stride (ints) >= 64 MB >= n
+    static constexpr int RV = (MB + 3) / 4;  // int4 per lane per aligned row
+    static constexpr int RU = (64 * MB + 3 + 255) / 256;  // ... per row starting off 16 B
+    static constexpr int BS = 256 * RV;      // row length capacity (ints) >= 64 MB >= n
+    static constexpr int GUARD = VEC4 ? 0 : 4;  // ints before and after each buffer
+    static constexpr int STRIDE = BS + GUARD;   // buffer k starts at GUARD + k * STRIDE
+    static constexpr int LDS_INTS = GUARD + 2 * STRIDE;
 };
 
+// One row of D in flight. Rows are read as aligned 16-byte chunks: when the
+// row starts `shift` ints past a 16-byte boundary (n not a multiple of 4),
+// the chunks start at the aligned-down address and each int is written to
+// its own index of the LDS buffer, the few ints before 0 and past n landing
+// in the buffer's guard words. Chunk indices are clamped, so every load stays
+// inside the row's aligned span.
 template <int MB, bool VEC4>
 struct RowPipe {
-    int4 v[WaveCfg<MB>::RV];
+    static constexpr int R = VEC4 ? WaveCfg<MB, VEC4>::RV : WaveCfg<MB, VEC4>::RU;
+    int4 v[R];
+    int shift;
 
-    // issue the loads of one row of D (all in bounds: indices are clamped)
     __device__ inline void load(const int32_t *__restrict__ src, int n)
     {
         const int lane = threadIdx.x;
@@ -169,31 +184,35 @@ struct RowPipe {
             const int4 *s4 = reinterpret_cast<const int4 *>(src);
             const int q = (n >> 2) - 1;
 #pragma unroll
-            for (int k = 0; k < WaveCfg<MB>::RV; ++k) v[k] = s4[min(lane + 64 * k, q)];
+            for (int k = 0; k < R; ++k) v[k] = s4[min(lane + 64 * k, q)];
         } else {
+            const uintptr_t a = reinterpret_cast<uintptr_t>(src);
+            shift = int(a & 15) >> 2;
+            const int4 *s4 = reinterpret_cast<const int4 *>(a - uintptr_t(4 * shift));
+            const int q = ((shift + n + 3) >> 2) - 1;
 #pragma unroll
-            for (int k = 0; k < WaveCfg<MB>::RV; ++k) {
-                const int b = 4 * (lane + 64 * k);
-                v[k].x = src[min(b + 0, n - 1)];
-                v[k].y = src[min(b + 1, n - 1)];
-                v[k].z = src[min(b + 2, n - 1)];
-                v[k].w = src[min(b + 3, n - 1)];
-            }
+            for (int k = 0; k < R; ++k) v[k] = s4[min(lane + 64 * k, q)];
         }
     }
 
-    // write the row into a buffer of stride BS (entries past n are filler)
     __device__ inline void store(int32_t *dst, int n) const
     {
         const int lane = threadIdx.x;
-        int4 *d4 = reinterpret_cast<int4 *>(dst);
         if constexpr (VEC4) {
+            int4 *d4 = reinterpret_cast<int4 *>(dst);
             const int q = (n >> 2) - 1;
 #pragma unroll
-            for (int k = 0; k < WaveCfg<MB>::RV; ++k) d4[min(lane + 64 * k, q)] = v[k];
+            for (int k = 0; k < R; ++k) d4[min(lane + 64 * k, q)] = v[k];
         } else {
+            const int q = ((shift + n + 3) >> 2) - 1;
 #pragma unroll
-            for (int k = 0; k < WaveCfg<MB>::RV; ++k) d4[lane + 64 * k] = v[k];
+            for (int k = 0; k < R; ++k) {
+                const int e = 4 * min(lane + 64 * k, q) - shift;  // in [-3, n + 3)
+                dst[e] = v[k].x;
+                dst[e + 1] = v[k].y;
+                dst[e + 2] = v[k].z;
+                dst[e + 3] = v[k].w;
+            }
         }
     }
 };
@@ -233,9 +252,9 @@ template <int MB, bool VEC4, int M0, int BI>
 __device__ __forceinline__ void sweep_row(SweepState<MB, VEC4> &S, const int32_t *__restrict__ D,
                                           int32_t *bufs, const uint16_t *tour, int n, int i)
 {
-    constexpr int BS = WaveCfg<MB>::BS;
-    int32_t *cur = bufs + BI * BS;
-    const int32_t *prv = bufs + (1 - BI) * BS;
+    constexpr int ST = WaveCfg<MB, VEC4>::STRIDE;
+    int32_t *cur = bufs + BI * ST;
+    const int32_t *prv = bufs + (1 - BI) * ST;
     const int lane = threadIdx.x;
     constexpr int P = kPrefetch == 2 ? BI : 0;
     S.pipe[P].store(cur, n);  // row of x_i+1, loaded kPrefetch rows ago
@@ -283,7 +302,7 @@ __device__ __forceinline__ void sweep_phase(SweepState<MB, VEC4> &S, const int32
 template <int MB, bool VEC4>
 __device__ __forceinline__ void twoopt_wave_body(const Inst &I, int p)
 {
-    constexpr int BS = WaveCfg<MB>::BS;
+    constexpr int ST = WaveCfg<MB, VEC4>::STRIDE, GU = WaveCfg<MB, VEC4>::GUARD;
     const int32_t *__restrict__ D = I.D;
     const View st = I.st;
     const KParams kp = I.kp;
@@ -291,8 +310,9 @@ __device__ __forceinline__ void twoopt_wave_body(const Inst &I, int p)
     if (h->err || h->done || !h->ee_ran) return;
     const int n = st.n, ns = st.ns, lane = threadIdx.x;
     extern __shared__ __align__(16) unsigned char smem[];
-    int32_t *bufs = reinterpret_cast<int32_t *>(smem);  // [2][BS]
-    uint16_t *tour = reinterpret_cast<uint16_t *>(bufs + 2 * BS);
+    // [guard][buffer 0][guard][buffer 1][guard], buffer k at GU + k * ST
+    int32_t *bufs = reinterpret_cast<int32_t *>(smem) + GU;
+    uint16_t *tour = reinterpret_cast<uint16_t *>(bufs + 2 * ST);
     uint16_t *xg = st.X + size_t(p) * ns;
     for (int k = lane; k < n; k += 64) tour[k] = xg[k];
     compiler_fence();
@@ -316,10 +336,10 @@ __device__ __forceinline__ void twoopt_wave_body(const Inst &I, int p)
         }
         // g <- D[x_0][x_c+1]: the first term of row 0, one column to the right
         S.pipe[0].load(D + size_t(tour[0]) * n, n);
-        S.pipe[0].store(bufs + BS, n);
+        S.pipe[0].store(bufs + ST, n);
         compiler_fence();
 #pragma unroll
-        for (int m = 0; m < MB; ++m) S.g[m] = lds_word(bufs + BS, S.off(m));
+        for (int m = 0; m < MB; ++m) S.g[m] = lds_word(bufs + ST, S.off(m));
 #pragma unroll
         for (int k = 0; k < kPrefetch; ++k)
             if (k + 1 < n) S.pipe[k].load(D + size_t(tour[k + 1]) * n, n);
@@ -399,7 +419,7 @@ namespace {
 template <int MB, bool VEC4>
 hipError_t launch_wave(const Inst *one, const Batch &B, int grid, int max_ns, hipStream_t s)
 {
-    const size_t lds = size_t(WaveCfg<MB>::BS) * 4 * 2 + size_t(max_ns) * 2;
+    const size_t lds = size_t(WaveCfg<MB, VEC4>::GUARD + 2 * WaveCfg<MB, VEC4>::STRIDE) * 4 + size_t(max_ns) * 2;
     hipError_t e = allow_lds(k_2opt_wave<MB, VEC4>, lds);
     if (e == hipSuccess) e = allow_lds(k_2opt_wave_batch<MB, VEC4>, lds);
     if (e != hipSuccess || grid <= 0) return e;

@@ -267,3 +267,23 @@ def test_batch_matches_oracle(dp, graph):
         oracle.run(D, prm, ref, gens)
         bad = mismatches(dp.export_state(st, D.shape[0], prm["swarm_size"], stream), ref)
         assert not bad, f"instance {k} (n={D.shape[0]}): {bad}"
+
+
+def test_served_results_equal_single_solves(dp):
+    """A short stream through the re-planning server: every served plan equals
+    the plan of solving that request alone (and a tight budget forces several
+    batches)."""
+    from paper_1706_04399_amd import serve
+    reqs = serve.poisson_requests(12, rate=400.0, seed=9, n_lo=20, n_hi=120, swarm=32,
+                                  generations=15)
+    ex = serve.GpuExecutor(batched=True)
+    budget = 3 * max(ex.footprint(r) for r in reqs)
+    recs = serve.serve(reqs, ex, serve.Scheduler(budget, ex.footprint))
+    assert sorted(r.rid for r in recs) == list(range(12))
+    assert len({r.batch for r in recs}) >= 4
+    for rec in recs:
+        req = reqs[rec.rid]
+        D = dp.build_dist(req.scene)
+        st = dp.init_nn(D, req.params)
+        dp.run(D, req.params, st, req.params["max_generations"])
+        assert dp.get_best(st)[1] == rec.cost, rec.rid
