@@ -287,3 +287,35 @@ def test_served_results_equal_single_solves(dp):
         st = dp.init_nn(D, req.params)
         dp.run(D, req.params, st, req.params["max_generations"])
         assert dp.get_best(st)[1] == rec.cost, rec.rid
+
+
+def _costs(D, tours):
+    """Tour costs recomputed with numpy (independent of both implementations)."""
+    t = tours.astype(np.int64)
+    return D.astype(np.int64)[t, np.roll(t, -1, axis=1)].sum(axis=1)
+
+
+def test_workload3_full_length_properties(dp):
+    """The benchmark run itself (2000 generations, n = 1000, swarm 4096): too
+    long for the oracle, checked by properties that hold at any size."""
+    sc, prm = scenes.workload(3)
+    D = oracle.build_dist(sc)
+    Dg = _dev(D)
+    note("facade1000: full 2000-generation run")
+    state = dp.init_nn(Dg, prm)
+    dp.run(Dg, prm, state, prm["max_generations"])
+    ex = dp.export_state(state, sc.n, prm["swarm_size"])
+    info = dp.get_info(state)
+    n, S, G = sc.n, prm["swarm_size"], prm["max_generations"]
+    assert ex["generation"] == G and ex["done"] == 1
+    for name in ("X", "P"):
+        assert (np.sort(ex[name].astype(np.int64), axis=1) == np.arange(n)).all(), name
+    assert (np.sort(ex["G"].astype(np.int64)) == np.arange(n)).all()
+    assert np.array_equal(_costs(D, ex["X"]), ex["F"])
+    assert np.array_equal(_costs(D, ex["P"]), ex["FP"])
+    assert ex["best_cost"] == ex["FP"].min() == _costs(D, ex["G"][None, :])[0]
+    assert (np.diff(ex["trace"]) <= 0).all() and ex["trace"][-1] == ex["best_cost"]
+    assert (ex["FP"] <= ex["F"]).all()
+    assert info["sweeps"] == S * G                  # one complete sweep per particle
+    assert 0 < info["moves"] <= S * G
+    assert (ex["vlen"] <= n - 1).all()
