@@ -48,14 +48,71 @@ def hbm_traffic_per_launch():
     return int(b.group(1))
 
 
+def measure_ceilings():
+    """Measured rates of the memory paths (micro-benchmarks of
+    ``libceilings.so``), each timed with events on the stream it runs on:
+    16-byte reads streamed from L2 (a 16 MB buffer of which each XCD reads its
+    own 2 MB), random 4-byte reads over a 4 MB buffer (a distance matrix at
+    n = 1000), random 4-byte LDS reads within a 4 KB row per wave, and 16-byte
+    LDS writes of 4 KB rows. Occupancy of the LDS tests matches the
+    edge-exchange kernel (16 waves per CU)."""
+    import ctypes as C
+    import torch
+    lib = C.CDLL(os.path.join(ROOT, "paper_1706_04399_amd", "libceilings.so"))
+    u64, i32 = C.c_uint64, C.c_int32
+    lib.ceil_l2_stream.argtypes = [C.c_void_p, C.c_size_t, i32, i32, C.c_void_p, C.c_void_p]
+    lib.ceil_l2_gather.argtypes = [C.c_void_p, C.c_uint32, i32, i32, C.c_void_p, C.c_void_p]
+    lib.ceil_lds_gather.argtypes = [i32, i32, C.c_void_p, C.c_void_p]
+    lib.ceil_lds_write.argtypes = [i32, i32, C.c_void_p, C.c_void_p]
+    stream = torch.cuda.current_stream()
+    sh = C.c_void_p(stream.cuda_stream)
+    big = torch.randint(0, 1 << 20, (4 << 20,), dtype=torch.int32, device="cuda")   # 16 MB
+    mat = torch.randint(0, 1 << 20, (1 << 20,), dtype=torch.int32, device="cuda")   # 4 MB
+    sink = torch.zeros(1024 * 256, dtype=torch.int32, device="cuda")
+    blocks = 1024
+
+    def timed(call):
+        call()                                   # warm-up (and caches)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(3):
+            st = call()
+            if st != 0:
+                raise RuntimeError(f"ceiling kernel launch failed: {st}")
+        b.record(stream)
+        b.synchronize()
+        return a.elapsed_time(b) / 3 / 1e3      # seconds per launch
+
+    reps = 400
+    t = timed(lambda: lib.ceil_l2_stream(C.c_void_p(big.data_ptr()), big.numel() * 4, blocks, reps,
+                                         C.c_void_p(sink.data_ptr()), sh))
+    slice_bytes = big.numel() * 4 // blocks // 16384 * 16384
+    l2_stream = slice_bytes * blocks * reps / t / 1e9
+    reps = 64
+    t = timed(lambda: lib.ceil_l2_gather(C.c_void_p(mat.data_ptr()), mat.numel(), 2048, reps,
+                                         C.c_void_p(sink.data_ptr()), sh))
+    l2_gather = 2048 * 256 * reps * 16 * 4 / t / 1e9
+    reps = 2000
+    t = timed(lambda: lib.ceil_lds_gather(blocks, reps, C.c_void_p(sink.data_ptr()), sh))
+    lds_gather = blocks * 256 * reps * 16 / t / 1e9               # G reads/s
+    t = timed(lambda: lib.ceil_lds_write(blocks, reps, C.c_void_p(sink.data_ptr()), sh))
+    lds_write = blocks * 4 * reps * 4096 / t / 1e9               # GB/s
+    torch.cuda.synchronize()
+    return {"l2_stream_GBs": round(l2_stream, 1), "l2_random_gather_GBs": round(l2_gather, 1),
+            "lds_random_read_G_per_s": round(lds_gather, 1), "lds_row_write_GBs": round(lds_write, 1)}
+
+
 def cpu_baseline(seconds: float):
     """The oracle on the same workload, timed on the host cores for a bounded
-    number of generations."""
+    number of generations, then one more generation on a single thread."""
+    import ctypes as C
     import oracle
     from paper_1706_04399_amd import scenes
     sc, prm = scenes.workload(3)
     D = oracle.build_dist(sc)
     st = oracle.new_state(D, prm)
+    gomp = C.CDLL("libgomp.so.1")               # the OpenMP runtime the oracle runs on
+    threads = int(gomp.omp_get_max_threads())
     gens, t0 = 0, time.perf_counter()
     while gens < 40:
         oracle.generation(D, prm, st)
@@ -63,11 +120,17 @@ def cpu_baseline(seconds: float):
         if time.perf_counter() - t0 >= seconds:
             break
     dt = time.perf_counter() - t0
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    gomp.omp_set_num_threads(1)
+    t1 = time.perf_counter()
+    oracle.generation(D, prm, st)
+    dt1 = time.perf_counter() - t1
+    gomp.omp_set_num_threads(threads)
     return {"value": round(prm["swarm_size"] * gens / dt, 1), "unit": "particle-iters/s",
-            "cores": cores, "kind": "oracle",
+            "cores": threads, "kind": "oracle",
+            "value_1_core": round(prm["swarm_size"] / dt1, 1),
             "sample": f"generations 1-{gens} of the same workload (n=1000, swarm 4096, "
-                      f"edge exchange every generation), {dt:.1f} s"}
+                      f"edge exchange every generation) on {threads} threads, {dt:.1f} s; "
+                      f"generation {gens + 1} on 1 thread, {dt1:.1f} s"}
 
 
 def bench_batch(count: int, generations: int):
@@ -156,6 +219,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-ceilings", action="store_true",
+                    help="skip the memory-path micro-benchmarks")
     ap.add_argument("--batch", type=int, default=0,
                     help="run the batched workload with this many instances instead")
     ap.add_argument("--batch-generations", type=int, default=500)
@@ -227,6 +292,22 @@ def main():
         "phases_ms": {k: round(v, 2) for k, v in phases.items() if k.startswith("ms_")},
         "best_cost_mm": info1["best_cost"],
     }
+    if not args.no_ceilings:
+        c = measure_ceilings()
+        bpi = 4 * n * (n - 1)                       # algorithmic bytes per particle-iteration
+        per_launch = sweeps / launches              # sweeps in one exchange launch
+        # LDS time the exchange kernel cannot go below at the measured rates:
+        # one random read per exchange, one staged 4n-byte row per row
+        lds_s = per_launch * (n * (n - 3) / 2 / (c["lds_random_read_G_per_s"] * 1e9) +
+                              4 * n * (n - 2) / (c["lds_row_write_GBs"] * 1e9))
+        c.update({
+            "l2_stream_bound_piters_per_s": round(c["l2_stream_GBs"] * 1e9 / bpi, 1),
+            "l2_gather_bound_piters_per_s": round(c["l2_random_gather_GBs"] * 1e9 / bpi, 1),
+            "exchange_lds_bound_us": round(lds_s * 1e6, 1),
+            "exchange_measured_us": round(avg_launch_s * 1e6, 1),
+            "exchange_frac_of_lds_bound": round(lds_s / avg_launch_s, 4),
+        })
+        line["ceilings"] = c
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(line), flush=True)

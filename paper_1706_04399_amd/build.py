@@ -15,6 +15,10 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libdpso.so")
+# memory-path micro-benchmarks for the benchmark's roofline report (not part of
+# the DPSO library)
+CEIL_SRC = os.path.join(PKG, "ceilings", "ceilings.hip")
+CEIL_LIB = os.path.join(PKG, "libceilings.so")
 ARCH = "gfx950"
 
 
@@ -29,24 +33,29 @@ def sources():
     return sorted(glob.glob(os.path.join(CSRC, "*.hip")))
 
 
-def command(out: str):
+def command(out: str, srcs=None):
     return [hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
             "-Wall", "-Wno-unused-result",
             # keep the compiler from forming packed fp32 instructions
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-            "-I", INCLUDE, "-I", CSRC, "-o", out] + sources()
+            "-I", INCLUDE, "-I", CSRC, "-o", out] + (srcs if srcs is not None else sources())
 
 
-def build(verbose: bool = False) -> str:
-    tmp = LIB + f".tmp{os.getpid()}"
-    cmd = command(tmp)
+def _compile(lib: str, srcs, verbose: bool):
+    tmp = lib + f".tmp{os.getpid()}"
+    cmd = command(tmp, srcs)
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed to build libdpso.so")
-    os.replace(tmp, LIB)
+        raise RuntimeError(f"hipcc failed to build {os.path.basename(lib)}")
+    os.replace(tmp, lib)
+
+
+def build(verbose: bool = False) -> str:
+    _compile(LIB, sources(), verbose)
+    _compile(CEIL_LIB, [CEIL_SRC], verbose)
     return LIB
 
 

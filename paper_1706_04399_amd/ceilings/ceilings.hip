@@ -1,0 +1,154 @@
+// Measured ceilings of the memory paths the swarm kernels use, for the
+// benchmark's roofline report. Not part of the DPSO library: every entry
+// point launches one micro-benchmark kernel on the caller's stream and
+// returns the launch status; the caller times it with events.
+//
+//   ceil_l2_stream   16-byte reads streamed over an L2-resident buffer
+//   ceil_l2_gather   random 4-byte reads over the same buffer (the access
+//                    pattern of a distance-matrix gather straight from memory)
+//   ceil_lds_gather  random 4-byte LDS reads within a 4 KB row per wave
+//                    (the edge-exchange gather)
+//   ceil_lds_write   16-byte LDS writes of whole 4 KB rows per wave (the
+//                    edge-exchange row staging)
+//
+// Every kernel accumulates what it reads and stores only if the sum equals a
+// value it never reaches, so the reads cannot be dropped and nothing is
+// written. Argument checks keep every access inside the buffers.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kRow = 1024;  // ints per LDS row (4 KB)
+constexpr int kNever = 0x7e5a1c3b;
+
+// Block b reads, on pass r, slice (b + 8r) mod nb. Blocks are dealt to the 8
+// XCDs round-robin, so a slice is always read by the same XCD (its L2 keeps
+// it) while a CU moves to a new slice every pass (no L1 reuse).
+__global__ __launch_bounds__(kThreads) void k_stream(const int4 *__restrict__ buf, int slice, int reps,
+                                                     int *sink)
+{
+    const int nb = gridDim.x;
+    int acc = 0;
+    for (int r = 0; r < reps; ++r) {
+        const int4 *p = buf + size_t((blockIdx.x + 8 * r) % nb) * slice;
+        for (int i = threadIdx.x; i < slice; i += 4 * kThreads) {  // slice % (4 * kThreads) == 0
+            int4 v[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) v[k] = p[i + k * kThreads];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) acc += v[k].x ^ v[k].y ^ v[k].z ^ v[k].w;
+        }
+    }
+    if (acc == kNever) sink[blockIdx.x] = acc;
+}
+
+// Addresses come from a per-lane xorshift sequence, independent of the data,
+// so many reads are in flight. words is a power of two.
+__global__ __launch_bounds__(kThreads) void k_gather(const int *__restrict__ buf, uint32_t words, int reps,
+                                                     int *sink)
+{
+    uint32_t s = (blockIdx.x * kThreads + threadIdx.x) * 2654435761u + 0x9e3779b9u;
+    int acc = 0;
+    for (int r = 0; r < reps; ++r) {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            s ^= s << 13;
+            s ^= s >> 17;
+            s ^= s << 5;
+            acc += buf[s & (words - 1)];
+        }
+    }
+    if (acc == kNever) sink[blockIdx.x] = acc;
+}
+
+// One 4 KB row per wave; each lane holds 16 random column offsets and walks
+// them with a per-pass stride, three VALU operations per read (as in the
+// edge-exchange sweep, where a read costs a few VALU operations too).
+__global__ __launch_bounds__(kThreads) void k_lds_gather(int reps, int *sink)
+{
+    __shared__ int row[kThreads / 64][kRow];
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    for (int k = l; k < kRow; k += 64) row[w][k] = k * 7 + w;
+    __syncthreads();
+    uint32_t s = (blockIdx.x * kThreads + threadIdx.x) * 2654435761u + 0x9e3779b9u;
+    uint32_t col[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        s ^= s << 13;
+        s ^= s >> 17;
+        s ^= s << 5;
+        col[k] = s;
+    }
+    int acc = 0;
+    uint32_t off = 0;
+    for (int r = 0; r < reps; ++r) {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) acc += row[w][(col[k] + off) & (kRow - 1)];
+        off += 97;
+    }
+    if (acc == kNever) sink[blockIdx.x * kThreads + threadIdx.x] = acc;
+}
+
+// Two 4 KB rows per wave written alternately with 16-byte stores.
+__global__ __launch_bounds__(kThreads) void k_lds_write(int reps, int *sink)
+{
+    __shared__ int4 rows[kThreads / 64][2][kRow / 4];
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    int4 v = make_int4(int(threadIdx.x), int(blockIdx.x), 1, 2);
+    for (int r = 0; r < reps; ++r) {
+        int4 *b = rows[w][r & 1];
+#pragma unroll
+        for (int k = 0; k < kRow / 4; k += 64) b[l + k] = v;
+        v.x += 1;
+        __asm__ volatile("" ::: "memory");  // every pass's stores are kept
+    }
+    __syncthreads();
+    const int4 u = rows[(w + 1) & 3][1][(l * 5) & (kRow / 4 - 1)];
+    if (u.x + u.y + u.z + u.w == kNever) sink[blockIdx.x * kThreads + threadIdx.x] = u.x;
+}
+
+}  // namespace
+
+extern "C" {
+
+// buf: device, `bytes` >= 16 KB * blocks; blocks a positive multiple of 8;
+// sink: device, >= blocks ints. A block's slice is bytes / blocks rounded
+// down to 16 KB; reads 16 KB * (bytes / blocks / 16 KB) * blocks * reps bytes.
+int ceil_l2_stream(const void *buf, size_t bytes, int blocks, int reps, int *sink, hipStream_t stream)
+{
+    if (!buf || !sink || blocks <= 0 || blocks % 8 != 0 || reps <= 0) return int(hipErrorInvalidValue);
+    const size_t slice = bytes / 16 / size_t(blocks) / (4 * kThreads) * (4 * kThreads);
+    if (slice == 0 || slice > 0x7fffffff) return int(hipErrorInvalidValue);
+    k_stream<<<blocks, kThreads, 0, stream>>>(static_cast<const int4 *>(buf), int(slice), reps, sink);
+    return int(hipGetLastError());
+}
+
+// buf: device, `words` ints, words a power of two; sink: >= blocks ints.
+// Reads blocks * 256 * reps * 16 ints.
+int ceil_l2_gather(const void *buf, uint32_t words, int blocks, int reps, int *sink, hipStream_t stream)
+{
+    if (!buf || !sink || blocks <= 0 || reps <= 0 || words == 0 || (words & (words - 1)) != 0)
+        return int(hipErrorInvalidValue);
+    k_gather<<<blocks, kThreads, 0, stream>>>(static_cast<const int *>(buf), words, reps, sink);
+    return int(hipGetLastError());
+}
+
+// sink: >= blocks * 256 ints. Reads blocks * 256 * reps * 16 LDS ints.
+int ceil_lds_gather(int blocks, int reps, int *sink, hipStream_t stream)
+{
+    if (!sink || blocks <= 0 || reps <= 0) return int(hipErrorInvalidValue);
+    k_lds_gather<<<blocks, kThreads, 0, stream>>>(reps, sink);
+    return int(hipGetLastError());
+}
+
+// sink: >= blocks * 256 ints. Writes blocks * 4 * reps * 4096 LDS bytes.
+int ceil_lds_write(int blocks, int reps, int *sink, hipStream_t stream)
+{
+    if (!sink || blocks <= 0 || reps <= 0) return int(hipErrorInvalidValue);
+    k_lds_write<<<blocks, kThreads, 0, stream>>>(reps, sink);
+    return int(hipGetLastError());
+}
+
+}  // extern "C"

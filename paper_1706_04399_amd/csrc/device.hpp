@@ -114,9 +114,26 @@ __device__ inline int64_t block_tour_cost(const int32_t *__restrict__ D, int n,
     return block_sum_i64(s, red);
 }
 
+// Marks p as pointing to global memory. A pointer loaded from memory (or
+// rebuilt from an integer) has no known address space, so the compiler would
+// access it with flat instructions, which also count against the LDS wait
+// counter and so stall LDS work behind outstanding memory loads.
+// The empty asm keeps the compiler from folding the two address-space
+// casts back into the original pointer; p must be uniform (it is kept in
+// scalar registers).
+template <class T>
+__device__ inline T *global_ptr(T *p)
+{
+    typedef __attribute__((address_space(1))) T GT;
+    GT *g = (GT *)p;
+    __asm__("" : "+s"(g));
+    return (T *)g;
+}
+
 // Instance and local index of block b in a batched launch (binary search
-// over the prefix table; uniform across the workgroup).
-__device__ inline const Inst &batch_pick(const Batch &B, int b, int &local)
+// over the prefix table; uniform across the workgroup). The descriptor's
+// pointers are returned marked as global.
+__device__ inline Inst batch_pick(const Batch &B, int b, int &local)
 {
     int lo = 0, hi = B.count - 1;
     while (lo < hi) {
@@ -127,14 +144,28 @@ __device__ inline const Inst &batch_pick(const Batch &B, int b, int &local)
             hi = mid - 1;
     }
     local = b - B.first[lo];
-    return B.inst[lo];
+    Inst I = B.inst[lo];
+    I.D = global_ptr(I.D);
+    View &v = I.st;
+    v.hdr = global_ptr(v.hdr);
+    v.X = global_ptr(v.X);
+    v.P = global_ptr(v.P);
+    v.G = global_ptr(v.G);
+    v.V = global_ptr(v.V);
+    v.VL = global_ptr(v.VL);
+    v.flags = global_ptr(v.flags);
+    v.keep = global_ptr(v.keep);
+    v.F = global_ptr(v.F);
+    v.FP = global_ptr(v.FP);
+    v.trace = global_ptr(v.trace);
+    return I;
 }
 
 // Lets `kernel` take `bytes` of dynamic LDS (gfx950 has 160 KiB per CU).
 template <typename Kernel>
 inline hipError_t allow_lds(Kernel kernel, size_t bytes)
 {
-    if (bytes <= 65536) return hipSuccess;
+    if (bytes <= 60 * 1024) return hipSuccess;  // leaves room for static LDS
     return hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
                                hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
 }

@@ -18,37 +18,79 @@ __device__ inline bool mutation_generation(const KParams &kp, int t)
 }
 
 // Fisher-Yates shuffle of the identity into `tour` (LDS) with the stream
-// (p, t, purpose): for i = n-1 down to 1 exchange places i and
-// uniform(i+1), uniform(m) being the high word of draw * m. The draws are
-// generated by the whole workgroup into `draws` (LDS, n - 1 entries); the
-// exchanges are a serial chain done by thread 0.
-__device__ void fisher_yates(uint16_t *tour, uint32_t *draws, int n, const KParams &kp, int p, int t,
-                             uint64_t purpose)
+// (p, t, purpose): for i = n-1 down to 1 exchange places i and j_i =
+// uniform(i+1), uniform(m) being the high word of draw * m.
+//
+// The exchanges are not replayed one by one. Step i fixes place i for good,
+// so tour[i] is what place j_i holds just before step i. Let T(q) be the set
+// of steps i > q with j_i = q, and W(i) what place i holds just before step i
+// (for i = 0: at the end). Place q starts as q and, at each step of T(q) in
+// decreasing order, hands its content to that step's place and takes that
+// place's content W(step). Hence
+//   W(i)    = W(min T(i)), or i when T(i) is empty;
+//   tour[i] = W(i) if j_i = i (and for i = 0); otherwise W(u) with u the
+//             smallest step of T(j_i) above i, or j_i when there is none.
+// The sets T(q) are built as per-place lists with LDS atomic exchanges (their
+// order does not matter: only minima are taken; a set has about ln(n / q)
+// members), and the chains of W are resolved by pointer jumping.
+// `work` holds 14 * ns bytes.
+constexpr uint16_t kNone = 0xffffu;
+
+__device__ __forceinline__ void fisher_yates(uint16_t *tour, unsigned char *work, int n, int ns,
+                                             const KParams &kp, int p, int t, uint64_t purpose)
 {
+    uint32_t *head = reinterpret_cast<uint32_t *>(work);
+    uint16_t *jv = reinterpret_cast<uint16_t *>(work + size_t(ns) * 4);
+    uint16_t *nxt = jv + ns, *up = nxt + ns, *wa = up + ns, *wb = wa + ns;
+    for (int q = threadIdx.x; q < n; q += blockDim.x) head[q] = kNone;
+    if (threadIdx.x == 0) jv[0] = 0;
+    // step i uses draw n-1-i of the stream
     const int nblk = (n - 1 + 7) / 8;
     for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
         const Philox4 r = philox4x64_10(kp.seed, kp.instance, uint64_t(b), uint64_t(p), uint64_t(t), purpose);
-        for (int i = 0; i < 8; ++i) {
-            const int idx = b * 8 + i;
-            if (idx < n - 1) draws[idx] = draw_from_block(r, i);
+        for (int k = 0; k < 8; ++k) {
+            const int i = n - 1 - (b * 8 + k);
+            if (i >= 1) jv[i] = uint16_t(scale_draw(draw_from_block(r, k), uint32_t(i + 1)));
         }
     }
-    for (int k = threadIdx.x; k < n; k += blockDim.x) tour[k] = uint16_t(k);
     __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int i = n - 1; i >= 1; --i) {
-            const int j = int(scale_draw(draws[n - 1 - i], uint32_t(i + 1)));
-            const uint16_t tmp = tour[i];
-            tour[i] = tour[j];
-            tour[j] = tmp;
+    for (int i = threadIdx.x + 1; i < n; i += blockDim.x)
+        if (jv[i] < i) nxt[i] = uint16_t(atomicExch(head + jv[i], uint32_t(i)));
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        uint32_t m = kNone;
+        for (uint32_t c = head[i]; c != kNone; c = nxt[c]) m = min(m, c);
+        wa[i] = m == kNone ? uint16_t(i) : uint16_t(m);
+        uint32_t u = kNone;
+        const uint32_t q = jv[i];
+        if (q < uint32_t(i))
+            for (uint32_t c = head[q]; c != kNone; c = nxt[c])
+                if (c > uint32_t(i)) u = min(u, c);
+        up[i] = uint16_t(u);
+    }
+    __syncthreads();
+    // every chain i -> min T(i) -> ... ends at a place with empty T; at most
+    // ceil(log2 n) + 1 rounds
+    for (int round = 0; round < 16; ++round) {
+        int changed = 0;
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            const uint16_t a = wa[i], c = wa[a];
+            wb[i] = c;
+            changed |= c != a;
         }
+        uint16_t *tmp = wa; wa = wb; wb = tmp;
+        if (!__syncthreads_or(changed)) break;
+    }
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const uint16_t q = jv[i];
+        tour[i] = (i == 0 || q == i) ? wa[i] : up[i] != kNone ? wa[up[i]] : q;
     }
     __syncthreads();
 }
 
 // Writes a tour of LDS into X (and P), its cost into F (and FP); returns
 // the cost to every thread.
-__device__ int64_t store_particle(const int32_t *__restrict__ D, View st, int p, const uint16_t *tour,
+__device__ __forceinline__ int64_t store_particle(const int32_t *__restrict__ D, View st, int p, const uint16_t *tour,
                                   bool also_pbest, int64_t *red)
 {
     const int n = st.n;
@@ -140,8 +182,7 @@ __device__ __forceinline__ void init_body(const Inst &I, int p)
             __syncthreads();
         }
     } else {
-        uint32_t *draws = reinterpret_cast<uint32_t *>(smem + size_t(st.ns) * 2);
-        fisher_yates(tour, draws, n, kp, p, 0, kInit);
+        fisher_yates(tour, smem + size_t(st.ns) * 2, n, st.ns, kp, p, 0, kInit);
     }
     store_particle(D, st, p, tour, true, redi);
 }
@@ -221,7 +262,7 @@ __device__ MoveLds carve_move_lds(unsigned char *base, int ns)
 
 // Exclusive prefix count of the kEmit marks of rho[0..n) into rank[];
 // returns the total. Each thread takes a contiguous chunk.
-__device__ int block_rank(const uint16_t *rho, uint16_t *rank, int n, int *wsum)
+__device__ __forceinline__ int block_rank(const uint16_t *rho, uint16_t *rank, int n, int *wsum)
 {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int chunk = (n + kMoveThreads - 1) / kMoveThreads;
@@ -263,7 +304,7 @@ __device__ int block_rank(const uint16_t *rho, uint16_t *rank, int n, int *wsum)
 // when `whole` says the prefix is the whole list whatever its length (then
 // cur = to and nothing else is computed).
 template <int EPT, class Pick>
-__device__ int partial_toward(const uint16_t *from, const uint16_t *posf, const uint16_t *to, int n,
+__device__ __forceinline__ int partial_toward(const uint16_t *from, const uint16_t *posf, const uint16_t *to, int n,
                               Pick pick, bool whole, MoveLds &L)
 {
     if (whole) {
@@ -273,32 +314,35 @@ __device__ int partial_toward(const uint16_t *from, const uint16_t *posf, const 
     }
     uint32_t *ea = L.e0, *eb = L.e1;
     // (jump target, largest position seen) packed in one word; the window
-    // starts as {p} and doubles every round
+    // starts as {p} and doubles every round. A thread keeps its own words in
+    // registers; the buffers only serve the other threads' reads.
+    uint32_t e[EPT];
     DPSO_EACH(p)
     {
         const uint16_t r = posf[to[p]];
         L.rho[p] = r;
-        ea[p] = uint32_t(r) | (uint32_t(p) << 16);
+        e[e_] = uint32_t(r) | (uint32_t(p) << 16);
+        ea[p] = e[e_];
     }
     __syncthreads();
     // Stop when no window maximum grows: then every window's maximum equals
     // the next window's along the jumps, i.e. the whole cycle's maximum.
     for (int span = 1; span < n; span <<= 1) {
-        uint32_t e[EPT], f[EPT];
+        uint32_t f[EPT];
         int grew = 0;
-        DPSO_EACH(p) e[e_] = ea[p];
         DPSO_EACH(p) f[e_] = ea[e[e_] & 0xffffu];
         DPSO_EACH(p)
         {
             const uint32_t m = max(e[e_] >> 16, f[e_] >> 16);
-            eb[p] = (f[e_] & 0xffffu) | (m << 16);
             grew |= m != (e[e_] >> 16);
+            e[e_] = (f[e_] & 0xffffu) | (m << 16);
+            eb[p] = e[e_];
         }
         uint32_t *t = ea; ea = eb; eb = t;
         if (!vote_any(L, grew != 0)) break;
     }
     DPSO_EACH(p)
-    if ((ea[p] >> 16) != uint32_t(p)) L.rho[p] |= kEmit;
+    if ((e[e_] >> 16) != uint32_t(p)) L.rho[p] |= kEmit;
     __syncthreads();
     uint16_t *rank = reinterpret_cast<uint16_t *>(eb);  // eb is free here
     const int len = block_rank(L.rho, rank, n, L.wsum);
@@ -317,22 +361,22 @@ __device__ int partial_toward(const uint16_t *from, const uint16_t *posf, const 
     // cycle keeps its largest position unfixed, so ceil(log2 n) + 1 rounds
     // suffice; the cap only bounds the loop on a corrupted state.
     uint16_t *ja = reinterpret_cast<uint16_t *>(ea), *jb = reinterpret_cast<uint16_t *>(eb);
+    uint16_t j[EPT];
     DPSO_EACH(p)
     {
         const uint16_t r = L.rho[p] & kLabel;
-        ja[p] = r | (L.rho[r] & kFixed);
+        j[e_] = r | (L.rho[r] & kFixed);
+        ja[p] = j[e_];
     }
     __syncthreads();
     for (int round = 0; round < 20; ++round) {
-        uint16_t e[EPT], f[EPT];
         int pending = 0;
-        DPSO_EACH(p) e[e_] = ja[p];
-        DPSO_EACH(p) f[e_] = (e[e_] & kFixed) ? ja[e[e_] & kLabel] : e[e_];
         DPSO_EACH(p)
         {
-            jb[p] = f[e_];
-            pending |= f[e_] & kFixed;
+            if (j[e_] & kFixed) j[e_] = ja[j[e_] & kLabel];
+            pending |= j[e_] & kFixed;
         }
+        DPSO_EACH(p) jb[p] = j[e_];
         uint16_t *t = ja; ja = jb; jb = t;
         if (!vote_any(L, pending != 0)) break;
     }
@@ -342,7 +386,7 @@ __device__ int partial_toward(const uint16_t *from, const uint16_t *posf, const 
         if (r & kFixed)
             L.cur[p] = to[p];
         else
-            L.cur[ja[p] & kLabel] = from[r & kLabel];
+            L.cur[j[e_] & kLabel] = from[r & kLabel];
     }
     __syncthreads();
     return len;
@@ -518,8 +562,7 @@ __device__ __forceinline__ void mut_apply_body(const Inst &I, int p)
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int64_t redi[4];
     uint16_t *tour = reinterpret_cast<uint16_t *>(smem);
-    uint32_t *draws = reinterpret_cast<uint32_t *>(smem + size_t(st.ns) * 2);
-    fisher_yates(tour, draws, n, kp, p, t, kMut);
+    fisher_yates(tour, smem + size_t(st.ns) * 2, n, st.ns, kp, p, t, kMut);
     const int64_t cf = store_particle(D, st, p, tour, false, redi);
     const bool better = cf < st.FP[p];
     if (better)
@@ -626,8 +669,8 @@ DPSO_KERNELS(k_end, 64, end_body(I))
 
 // ---------------------------------------------------------------- launchers
 
-size_t init_lds_bytes(int ns) { return size_t(ns) * 2 + size_t(ns) * 4; }
-size_t mut_lds_bytes(int ns) { return size_t(ns) * 2 + size_t(ns) * 4; }
+size_t init_lds_bytes(int ns) { return size_t(ns) * 2 + size_t(ns) * 14; }
+size_t mut_lds_bytes(int ns) { return size_t(ns) * 2 + size_t(ns) * 14; }
 
 namespace {
 

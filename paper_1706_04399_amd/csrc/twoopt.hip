@@ -186,9 +186,10 @@ struct RowPipe {
 #pragma unroll
             for (int k = 0; k < R; ++k) v[k] = s4[min(lane + 64 * k, q)];
         } else {
-            const uintptr_t a = reinterpret_cast<uintptr_t>(src);
-            shift = int(a & 15) >> 2;
-            const int4 *s4 = reinterpret_cast<const int4 *>(a - uintptr_t(4 * shift));
+            shift = int(reinterpret_cast<uintptr_t>(src) & 15) >> 2;
+            // pointer arithmetic (not an integer round trip) keeps the
+            // global address space, so these are global, not flat, loads
+            const int4 *s4 = reinterpret_cast<const int4 *>(src - shift);
             const int q = ((shift + n + 3) >> 2) - 1;
 #pragma unroll
             for (int k = 0; k < R; ++k) v[k] = s4[min(lane + 64 * k, q)];

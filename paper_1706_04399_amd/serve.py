@@ -7,7 +7,9 @@ serves a stream of plan requests on one GPU:
 * requests wait in arrival order; each time the GPU is free the scheduler
   admits the waiting requests first come, first served, while the device
   footprint of the batch (swarm state + distance matrix + distance-builder
-  workspace) stays within a budget; at least one request is always admitted;
+  workspace) stays within a budget; a request whose footprint alone exceeds
+  the budget can never run and is rejected (status ``E_ADMIT``), so the head
+  of the queue always fits and every admission round admits at least one;
 * the admitted requests run as one batch (`dpso_run_batch`), distance
   matrices of scenes already resident are reused (re-planning on a known
   scene skips the distance build);
@@ -41,6 +43,9 @@ class Request:
         return self.scene.n
 
 
+E_ADMIT = -6   # rejected at admission: footprint above the whole budget
+
+
 @dataclasses.dataclass
 class Record:
     rid: int
@@ -50,6 +55,7 @@ class Record:
     done: float
     cost: int
     batch: int
+    status: int = 0   # 0 served, E_ADMIT rejected
 
     @property
     def latency(self) -> float:
@@ -77,18 +83,23 @@ def poisson_requests(count, rate, seed=5, n_lo=50, n_hi=800, swarm=512, generati
 
 
 class Scheduler:
-    """First come, first served admission under a device-memory budget."""
+    """First come, first served admission under a device-memory budget.
+    Requests that exceed the budget on their own are moved to `rejected`."""
 
     def __init__(self, budget_bytes: int, footprint, max_batch: int = 1024):
         self.budget = int(budget_bytes)
         self.footprint = footprint
         self.max_batch = int(max_batch)
+        self.rejected = []
 
     def admit(self, queue: collections.deque) -> list:
         batch, used = [], 0
         while queue and len(batch) < self.max_batch:
             need = self.footprint(queue[0])
-            if batch and used + need > self.budget:
+            if need > self.budget:
+                self.rejected.append(queue.popleft())
+                continue
+            if used + need > self.budget:
                 break
             batch.append(queue.popleft())
             used += need
@@ -109,6 +120,12 @@ def serve(requests, executor, scheduler: Scheduler, clock=time.perf_counter, sle
             sleep(max(0.0, pending[0].arrival - now))
             continue
         batch = scheduler.admit(queue)
+        for req in scheduler.rejected:
+            now = clock() - t0
+            records.append(Record(req.rid, req.n, req.arrival, now, now, -1, -1, E_ADMIT))
+        scheduler.rejected.clear()
+        if not batch:
+            continue
         start = clock() - t0
         costs = executor.solve(batch)
         done = clock() - t0
@@ -119,16 +136,18 @@ def serve(requests, executor, scheduler: Scheduler, clock=time.perf_counter, sle
 
 
 def summary(records, warmup: int = 0) -> dict:
-    """Latency percentiles and throughput over the requests after `warmup`."""
-    rs = sorted(records, key=lambda r: r.rid)[warmup:]
+    """Latency percentiles and throughput over the served requests after
+    `warmup` (rejected requests are counted, not timed)."""
+    after = sorted(records, key=lambda r: r.rid)[warmup:]
+    rs = [r for r in after if r.status == 0]
     if not rs:
-        return {}
+        return {"requests": 0, "rejected": len(after)}
     lat = np.array([r.latency for r in rs])
     span = max(r.done for r in rs) - min(r.arrival for r in rs)
     return {"requests": len(rs), "p50_ms": float(np.percentile(lat, 50) * 1e3),
             "p99_ms": float(np.percentile(lat, 99) * 1e3), "mean_ms": float(lat.mean() * 1e3),
             "max_ms": float(lat.max() * 1e3), "solves_per_s": len(rs) / span if span > 0 else 0.0,
-            "batches": len({r.batch for r in rs}),
+            "batches": len({r.batch for r in rs}), "rejected": len(after) - len(rs),
             "mean_batch": len(rs) / max(1, len({r.batch for r in rs}))}
 
 

@@ -156,6 +156,16 @@ def test_edge_cases(dp, name, n, S, gens, kw):
     lockstep(dp, D, prm, sorted({1, 2, 3, gens // 2 or 1, gens}), name)
 
 
+@pytest.mark.parametrize("n", [4096, 3001])
+def test_largest_sizes(dp, n):
+    """The largest supported n (and a ragged one near it): row-kernel edge
+    exchange on every generation, a mutation generation, LDS at its largest."""
+    D = scenes.random_dist(n, seed=n)
+    prm = scenes.swarm_params(8, 3, seed=5, instance=n, ee_trigger=scenes.EE_ALWAYS,
+                              det_permille=250)
+    lockstep(dp, D, prm, [1, 3], f"n{n}")
+
+
 def test_collapsed_swarm_mutation(dp):
     """All particles identical at a mutation generation: one is kept."""
     n, S = 48, 96

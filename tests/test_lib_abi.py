@@ -117,3 +117,23 @@ def test_batch_validation(dp):
     # items with zero swarm size are rejected before any device work
     assert L.dpso_run_batch(items, 2, 1, fake, need, None) == dp.E_INVAL
     assert L.dpso_run_batch(items, 2, -1, fake, need, None) == dp.E_INVAL
+
+
+def test_ceiling_benchmarks_load_and_check_arguments():
+    """The memory-path micro-benchmarks the benchmark uses for its ceilings:
+    exported, and invalid arguments are rejected before any launch."""
+    raw = C.CDLL(os.path.join(ROOT, "paper_1706_04399_amd", "libceilings.so"))
+    for name in ("ceil_l2_stream", "ceil_l2_gather", "ceil_lds_gather", "ceil_lds_write"):
+        assert hasattr(raw, name), name
+    vp, i32 = C.c_void_p, C.c_int32
+    raw.ceil_l2_stream.argtypes = [vp, C.c_size_t, i32, i32, vp, vp]
+    raw.ceil_l2_gather.argtypes = [vp, C.c_uint32, i32, i32, vp, vp]
+    raw.ceil_lds_gather.argtypes = [i32, i32, vp, vp]
+    raw.ceil_lds_write.argtypes = [i32, i32, vp, vp]
+    fake = vp(256)                     # never dereferenced: rejected first
+    assert raw.ceil_l2_stream(None, 1 << 24, 1024, 1, fake, None) != 0
+    assert raw.ceil_l2_stream(fake, 1 << 24, 1020, 1, fake, None) != 0   # not a multiple of 8
+    assert raw.ceil_l2_stream(fake, 1 << 10, 1024, 1, fake, None) != 0   # slice below 16 KB
+    assert raw.ceil_l2_gather(fake, 1000, 8, 1, fake, None) != 0         # not a power of two
+    assert raw.ceil_lds_gather(0, 1, fake, None) != 0
+    assert raw.ceil_lds_write(8, 0, fake, None) != 0

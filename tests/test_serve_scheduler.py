@@ -45,7 +45,13 @@ def test_admission_respects_budget_and_order():
     assert [r.rid for r in sched.admit(q)] == [4]
     big = serve.Scheduler(budget_bytes=50, footprint=lambda r: 100)
     q = collections.deque(_reqs([0.0] * 2))
-    assert [r.rid for r in big.admit(q)] == [0]          # always admits one
+    assert big.admit(q) == [] and not q                  # can never fit: rejected
+    assert [r.rid for r in big.rejected] == [0, 1]
+    mixed = serve.Scheduler(budget_bytes=150, footprint=lambda r: 200 if r.rid == 1 else 100)
+    q = collections.deque(_reqs([0.0] * 4))
+    assert [r.rid for r in mixed.admit(q)] == [0]        # 1 rejected, 2 does not fit beside 0
+    assert [r.rid for r in mixed.rejected] == [1]
+    assert [r.rid for r in mixed.admit(q)] == [2]
     capped = serve.Scheduler(budget_bytes=10 ** 9, footprint=lambda r: 1, max_batch=3)
     q = collections.deque(_reqs([0.0] * 7))
     assert [len(capped.admit(q)) for _ in range(3)] == [3, 3, 1]
@@ -84,3 +90,16 @@ def test_poisson_requests_shape():
     assert all(50 <= r.n <= 800 for r in reqs)
     assert 0.2 < arr[-1] < 2.0                    # about 40 / 50 s
     assert len({r.key for r in reqs}) == 40
+
+
+def test_rejected_requests_are_recorded_not_timed():
+    clock = FakeClock()
+    ex = StubExecutor(clock)
+    sched = serve.Scheduler(budget_bytes=100, footprint=lambda r: 1000 if r.rid % 2 else 10)
+    recs = serve.serve(_reqs([0.0, 0.0, 0.1, 0.2]), ex, sched, clock=clock, sleep=clock.sleep)
+    by = {r.rid: r for r in recs}
+    assert by[1].status == serve.E_ADMIT and by[3].status == serve.E_ADMIT
+    assert by[0].status == 0 and by[2].status == 0
+    assert all(rid in (0, 2) for b in ex.batches for rid in b)
+    s = serve.summary(recs)
+    assert s["requests"] == 2 and s["rejected"] == 2
