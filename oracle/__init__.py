@@ -35,7 +35,8 @@ class Params(C.Structure):
                 ("w_q16", C.c_uint32), ("phi1_q16", C.c_uint32), ("phi2_q16", C.c_uint32),
                 ("mutation_period", C.c_int32), ("ee_trigger", C.c_int32),
                 ("ee_max_moves", C.c_int32), ("stall_limit", C.c_int32),
-                ("det_permille", C.c_int32), ("seed", C.c_uint64), ("instance", C.c_uint64)]
+                ("det_permille", C.c_int32), ("seed", C.c_uint64), ("instance", C.c_uint64),
+                ("ee_neighbourhood", C.c_int32), ("mutation_swaps", C.c_int32)]
 
 
 class _State(C.Structure):
@@ -67,6 +68,10 @@ def lib():
             "or_fisher_yates": (None, [i32, u64, u64, u64, u64, u64, P]),
             "or_best_2opt": (i64, [P, i32, P, P, P]),
             "or_edge_exchange": (i32, [P, i32, P, P, i32, P]),
+            "or_swap_delta": (i64, [P, i32, P, i32, i32]),
+            "or_best_swap": (i64, [P, i32, P, P, P]),
+            "or_node_exchange": (i32, [P, i32, P, P, i32, P]),
+            "or_disturb": (None, [i32, i32, u64, u64, u64, u64, u64, P]),
             "or_update_gbest": (i32, [P]),
             "or_check_params": (i32, [P, i32]),
             "or_init": (i32, [P, P, P]),
@@ -96,7 +101,7 @@ def _i32(a) -> np.ndarray:
 
 
 def params(d: dict) -> Params:
-    return Params(**{k: d[k] for k, _ in Params._fields_})
+    return Params(**{k: d.get(k, 0) for k, _ in Params._fields_})
 
 
 # ----------------------------------------------------------------- primitives
@@ -168,6 +173,33 @@ def edge_exchange(D, x, F, max_moves):
     sw = C.c_int64(0)
     m = lib().or_edge_exchange(_p(D), D.shape[0], _p(y), C.byref(f), max_moves, C.byref(sw))
     return y, f.value, m, sw.value
+
+
+def swap_delta(D, x, i, j) -> int:
+    D = _i32(D)
+    return int(lib().or_swap_delta(_p(D), D.shape[0], _p(_i32(x)), i, j))
+
+
+def best_swap(D, x):
+    D = _i32(D)
+    bi, bj = C.c_int32(), C.c_int32()
+    d = lib().or_best_swap(_p(D), D.shape[0], _p(_i32(x)), C.byref(bi), C.byref(bj))
+    return int(d), bi.value, bj.value
+
+
+def node_exchange(D, x, F, max_moves):
+    D = _i32(D)
+    y = _i32(x).copy()
+    f = C.c_int64(F)
+    sw = C.c_int64(0)
+    m = lib().or_node_exchange(_p(D), D.shape[0], _p(y), C.byref(f), max_moves, C.byref(sw))
+    return y, f.value, m, sw.value
+
+
+def disturb(x, k, seed, instance, p, t, purpose):
+    y = _i32(x).copy()
+    lib().or_disturb(len(y), k, seed, instance, p, t, purpose, _p(y))
+    return y
 
 
 def round_len(dx, dy, dz) -> int:

@@ -27,12 +27,15 @@
 enum { OR_OK = 0, OR_EINVAL = -1, OR_ERANGE = -2, OR_ENOMEM = -3 };
 enum { PURPOSE_INIT = 0, PURPOSE_VEL = 1, PURPOSE_MUT = 2 };
 enum { EE_OFF = 0, EE_ON_STALL = 1, EE_ALWAYS = 2 };
+enum { NB_TWO_OPT = 0, NB_NODE_SWAP = 1 };
 
 typedef struct {
     int32_t swarm_size, max_generations;
     uint32_t w_q16, phi1_q16, phi2_q16;
     int32_t mutation_period, ee_trigger, ee_max_moves, stall_limit, det_permille;
     uint64_t seed, instance;
+    int32_t ee_neighbourhood; /* NB_TWO_OPT (segment reversal) or NB_NODE_SWAP   */
+    int32_t mutation_swaps;   /* 0: reshuffle; k > 0: k random position exchanges */
 } or_params;
 
 typedef struct {
@@ -284,6 +287,82 @@ int32_t or_edge_exchange(const int32_t *D, int32_t n, int32_t *x, int64_t *F, in
 }
 
 /* ---------------------------------------------------------------------------
+ * Node-swap neighbourhood (the edge-exchange kernel and pseudo code of Sect.
+ * 3.3 exchange the nodes at two positions and keep the best): exchanging the
+ * labels at positions i < j changes only the closing edges k -> k+1 (mod n)
+ * that touch i or j, so the cost changes by the sum over those distinct edge
+ * indices {i-1, i, j-1, j} (mod n) of new minus old edge cost. This is
+ * C(swapped) - C(x) exactly, adjacent and wrapping pairs included.
+ * ------------------------------------------------------------------------- */
+int64_t or_swap_delta(const int32_t *D, int32_t n, const int32_t *x, int32_t i, int32_t j)
+{
+    int32_t edges[4] = {(i + n - 1) % n, i, (j + n - 1) % n, j}, m = 0;
+    int32_t uniq[4];
+    for (int32_t a = 0; a < 4; a++) {
+        int32_t seen = 0;
+        for (int32_t b = 0; b < m; b++) seen |= uniq[b] == edges[a];
+        if (!seen) uniq[m++] = edges[a];
+    }
+    int64_t delta = 0;
+    for (int32_t a = 0; a < m; a++) {
+        int32_t k = uniq[a], k1 = (k + 1) % n;
+        int32_t u = x[k], v = x[k1];                      /* before */
+        int32_t u2 = k == i ? x[j] : k == j ? x[i] : u;   /* after  */
+        int32_t v2 = k1 == i ? x[j] : k1 == j ? x[i] : v;
+        delta += (int64_t)D[(int64_t)u2 * n + v2] - D[(int64_t)u * n + v];
+    }
+    return delta;
+}
+
+/* Best exchange of two positions: minimum delta over 0 <= i < j < n, ties to
+ * the smallest i, then j. *bi = -1 when n < 2. */
+int64_t or_best_swap(const int32_t *D, int32_t n, const int32_t *x, int32_t *bi, int32_t *bj)
+{
+    int64_t best = 0;
+    *bi = -1; *bj = -1;
+    for (int32_t i = 0; i + 1 < n; i++)
+        for (int32_t j = i + 1; j < n; j++) {
+            int64_t delta = or_swap_delta(D, n, x, i, j);
+            if (*bi < 0 || delta < best) { best = delta; *bi = i; *bj = j; }
+        }
+    return best;
+}
+
+/* or_edge_exchange with the node-swap neighbourhood. */
+int32_t or_node_exchange(const int32_t *D, int32_t n, int32_t *x, int64_t *F, int32_t max_moves,
+                         int64_t *sweeps)
+{
+    int32_t moves = 0;
+    for (;;) {
+        int32_t i, j;
+        int64_t delta = or_best_swap(D, n, x, &i, &j);
+        if (sweeps) (*sweeps)++;
+        if (i < 0 || delta >= 0) break;
+        int32_t tmp = x[i]; x[i] = x[j]; x[j] = tmp;
+        *F += delta;
+        moves++;
+        if (max_moves > 0 && moves >= max_moves) break;
+    }
+    return moves;
+}
+
+/* Disturbance of a tour in randomly chosen dimensions (the reading of the
+ * mutation text of Sect. 3.2.2 as an alternative to a reshuffle): k
+ * exchanges of positions (uniform(n), uniform(n)), drawn in that order from
+ * the stream (p, t, purpose), applied one after another. */
+void or_disturb(int32_t n, int32_t k, uint64_t seed, uint64_t inst, uint64_t p, uint64_t t,
+                uint64_t purpose, int32_t *x)
+{
+    or_stream s;
+    stream_open(&s, seed, inst, p, t, purpose);
+    for (int32_t a = 0; a < k; a++) {
+        int32_t i = (int32_t)uniform_below(stream_next(&s), (uint32_t)n);
+        int32_t j = (int32_t)uniform_below(stream_next(&s), (uint32_t)n);
+        int32_t tmp = x[i]; x[i] = x[j]; x[j] = tmp;
+    }
+}
+
+/* ---------------------------------------------------------------------------
  * Swarm phases (pseudo code of the enhanced DPSO, Sect. 3.3).
  * ------------------------------------------------------------------------- */
 static int32_t *row32(int32_t *a, int32_t n, int32_t p) { return a + (int64_t)p * n; }
@@ -319,6 +398,8 @@ int32_t or_check_params(const or_params *prm, int32_t n)
     if (prm->mutation_period < 0 || prm->ee_trigger < 0 || prm->ee_trigger > 2) return OR_EINVAL;
     if (prm->ee_max_moves < 0 || prm->stall_limit < 0) return OR_EINVAL;
     if (prm->det_permille < 0 || prm->det_permille > 1000) return OR_EINVAL;
+    if (prm->ee_neighbourhood < NB_TWO_OPT || prm->ee_neighbourhood > NB_NODE_SWAP) return OR_EINVAL;
+    if (prm->mutation_swaps < 0 || prm->mutation_swaps > 65536) return OR_EINVAL;
     return OR_OK;
 }
 
@@ -418,9 +499,10 @@ static int cmp_by_cost(const void *pa, const void *pb)
  * worst two thirds): particles are ordered by (cost, index); a particle whose
  * tour equals that of an earlier particle of equal cost is a duplicate; the
  * first ceil(S/3) non-duplicates are kept and every other particle restarts
- * from a fresh shuffle with an empty velocity (its personal best is kept and
- * updated if the shuffle is strictly better). kept[p] (optional) receives 1
- * for kept particles. Returns the number of reshuffled particles. */
+ * from a fresh shuffle (or, with mutation_swaps = k > 0, is disturbed by k
+ * random position exchanges) with an empty velocity (its personal best is
+ * kept and updated if the new tour is strictly better). kept[p] (optional)
+ * receives 1 for kept particles. Returns the number of mutated particles. */
 int32_t or_mutation(const int32_t *D, const or_params *prm, or_state *st, int32_t t, int32_t *kept)
 {
     int32_t n = st->n, S = st->S;
@@ -442,7 +524,11 @@ int32_t or_mutation(const int32_t *D, const or_params *prm, or_state *st, int32_
     for (int32_t p = 0; p < S; p++) {
         if (keep[p]) continue;
         int32_t *x = row32(st->X, n, p);
-        or_fisher_yates(n, prm->seed, prm->instance, (uint64_t)p, (uint64_t)t, PURPOSE_MUT, x);
+        if (prm->mutation_swaps > 0)
+            or_disturb(n, prm->mutation_swaps, prm->seed, prm->instance, (uint64_t)p, (uint64_t)t,
+                       PURPOSE_MUT, x);
+        else
+            or_fisher_yates(n, prm->seed, prm->instance, (uint64_t)p, (uint64_t)t, PURPOSE_MUT, x);
         st->VL[p] = 0;
         st->F[p] = or_tour_cost(D, n, x);
         pbest_rule(st, p);
@@ -473,7 +559,10 @@ int32_t or_generation(const int32_t *D, const or_params *prm, or_state *st)
         #pragma omp parallel for schedule(dynamic) reduction(+ : sweeps, moves)
         for (int32_t p = 0; p < S; p++) {
             int64_t sw = 0;
-            moves += or_edge_exchange(D, n, row32(st->X, n, p), &st->F[p], prm->ee_max_moves, &sw);
+            int32_t *x = row32(st->X, n, p);
+            moves += prm->ee_neighbourhood == NB_NODE_SWAP
+                         ? or_node_exchange(D, n, x, &st->F[p], prm->ee_max_moves, &sw)
+                         : or_edge_exchange(D, n, x, &st->F[p], prm->ee_max_moves, &sw);
             sweeps += sw;
             pbest_rule(st, p);
         }
