@@ -59,6 +59,11 @@ typedef int32_t dpso_status;
 #define DPSO_EE_ON_STALL 1
 #define DPSO_EE_ALWAYS 2
 
+/* Edge-exchange neighbourhoods (dpso_params.ee_neighbourhood). */
+#define DPSO_NB_TWO_OPT 0   /* reverse a segment: the 2-opt search of Sect. 3.2.3      */
+#define DPSO_NB_NODE_SWAP 1 /* exchange the nodes at two positions: the edge-exchange
+                               kernel and pseudo code of Sect. 3.3                    */
+
 /* A scene (Sect. 2.1-2.2): viewpoint positions and axis-aligned box
  * obstacles in integer mm; boxes are inflated by clearance_mm (the UAV's
  * size). Coordinates must satisfy |c| < 2^26 after inflation, and
@@ -89,6 +94,11 @@ typedef struct {
     int32_t det_permille;    /* share of nearest-neighbour seeded particles (0..1000) */
     uint64_t seed;           /* Philox key word 0                                   */
     uint64_t instance;       /* Philox key word 1                                   */
+    int32_t ee_neighbourhood; /* DPSO_NB_*; both take the most improving move, ties
+                                 to the smallest first then second position          */
+    int32_t mutation_swaps;  /* 0: mutated particles restart from a shuffle; k > 0
+                                (at most 65536): they are disturbed by k exchanges of
+                                random positions instead (mutation text, Sect. 3.2.2) */
 } dpso_params;
 
 /* Progress of a swarm, read by dpso_get_info. */
@@ -98,9 +108,9 @@ typedef struct {
     int32_t stall;           /* generations since the global best last improved */
     int32_t done;            /* max_generations or stall_limit reached          */
     int64_t best_cost;       /* cost of the global best tour                    */
-    int64_t sweeps;          /* complete 2-opt neighbourhood searches run       */
-    int64_t moves;           /* 2-opt exchanges applied                         */
-    int64_t reshuffled;      /* particles restarted by mutation                 */
+    int64_t sweeps;          /* complete edge-exchange neighbourhood searches   */
+    int64_t moves;           /* edge exchanges applied                          */
+    int64_t reshuffled;      /* particles reshuffled or disturbed by mutation   */
 } dpso_info;
 
 /* Host view of a swarm state for dpso_export_state / dpso_import_state.

@@ -59,6 +59,10 @@ dpso_status check_params(const dpso_params *p, int32_t n)
     if (p->stall_limit < 0) return fail(DPSO_E_INVAL, "stall_limit must be >= 0");
     if (p->det_permille < 0 || p->det_permille > 1000)
         return fail(DPSO_E_INVAL, "det_permille = %d outside 0..1000", p->det_permille);
+    if (p->ee_neighbourhood != DPSO_NB_TWO_OPT && p->ee_neighbourhood != DPSO_NB_NODE_SWAP)
+        return fail(DPSO_E_INVAL, "ee_neighbourhood = %d is not a DPSO_NB_* value", p->ee_neighbourhood);
+    if (p->mutation_swaps < 0 || p->mutation_swaps > 65536)
+        return fail(DPSO_E_INVAL, "mutation_swaps = %d outside 0..65536", p->mutation_swaps);
     return DPSO_OK;
 }
 
@@ -77,6 +81,8 @@ dpso::KParams kernel_params(const dpso_params *p)
     k.max_generations = p->max_generations;
     int64_t m = (int64_t(p->swarm_size) * p->det_permille + 999) / 1000;
     k.det_count = int32_t(m < p->swarm_size ? m : p->swarm_size);
+    k.ee_neighbourhood = p->ee_neighbourhood;
+    k.mutation_swaps = p->mutation_swaps;
     return k;
 }
 
@@ -229,7 +235,7 @@ dpso_status plan_batch(const dpso_batch_item *items, int32_t count, void *d_work
         total += it.params.swarm_size;
         plan.max_ns = std::max(plan.max_ns, L.ns);
         plan.any_mutation |= it.params.mutation_period > 0;
-        const int c = dpso::exchange_class(it.n, it.d_dist);
+        const int c = dpso::exchange_class(it.n, it.d_dist, it.params.ee_neighbourhood);
         if (it.params.ee_trigger != DPSO_EE_OFF) {
             plan.any_exchange = true;
             auto ci = reinterpret_cast<dpso::Inst *>(host.data() + BL.cls_inst[c]);

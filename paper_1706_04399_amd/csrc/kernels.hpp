@@ -26,12 +26,16 @@ hipError_t launch_batch_gbest(const Batch &items, const Batch &instances, int to
                               hipStream_t s);
 hipError_t launch_batch_end(const Batch &items, const Batch &instances, int total, int max_ns, hipStream_t s);
 
-// twoopt.hip: the edge-exchange kernel depends on n (columns held per lane)
-// and on the alignment of D; instances of one class share a launch.
-constexpr int kExchangeClasses = 11;
-int exchange_class(int n, const int32_t *D);
+// twoopt.hip: the edge-exchange kernel depends on the neighbourhood, on n
+// (columns held per lane) and on the alignment of D; instances of one class
+// share a launch. The last class is the node-swap neighbourhood.
+constexpr int kExchangeClasses = 12;
+int exchange_class(int n, const int32_t *D, int neighbourhood);
 hipError_t launch_2opt(const Inst &I, hipStream_t s);
 hipError_t launch_batch_2opt(int cls, const Batch &items, int total, int max_ns, hipStream_t s);
+
+// nodeswap.hip: the node-swap neighbourhood (one workgroup per particle).
+hipError_t launch_node_swap(const Inst *one, const Batch &items, int grid, int max_ns, hipStream_t s);
 
 // dist.hip
 size_t dist_work_bytes(int32_t n, int32_t n_boxes);

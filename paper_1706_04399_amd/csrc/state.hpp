@@ -99,6 +99,7 @@ struct KParams {
     uint32_t w_q16, phi1_q16, phi2_q16;
     int32_t mutation_period, ee_trigger, ee_max_moves, stall_limit, max_generations;
     int32_t det_count;  // number of nearest-neighbour seeded particles
+    int32_t ee_neighbourhood, mutation_swaps;
 };
 
 // One swarm as the kernels see it: its distance matrix, state and params.

@@ -5,6 +5,8 @@
 // Every kernel of a generation reads the generation counter and the stop
 // flags from the state header on the device, so a whole run is enqueued
 // without any host round trip.
+#include <algorithm>
+
 #include "device.hpp"
 #include "kernels.hpp"
 
@@ -84,6 +86,36 @@ __device__ __forceinline__ void fisher_yates(uint16_t *tour, unsigned char *work
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
         const uint16_t q = jv[i];
         tour[i] = (i == 0 || q == i) ? wa[i] : up[i] != kNone ? wa[up[i]] : q;
+    }
+    __syncthreads();
+}
+
+// Disturbance by k exchanges of the positions (uniform(n), uniform(n)),
+// drawn in that order from the stream (p, t, purpose) and applied one after
+// another: the mutation text's reading of a perturbation in randomly chosen
+// dimensions. The workgroup draws 1024 exchanges at a time into `draws`
+// (LDS, 2048 entries); one thread applies them in order.
+__device__ __forceinline__ void disturb(uint16_t *tour, uint32_t *draws, int n, int k, const KParams &kp,
+                                        int p, int t, uint64_t purpose)
+{
+    constexpr int kChunk = 1024;
+    for (int a0 = 0; a0 < k; a0 += kChunk) {
+        const int m = min(kChunk, k - a0), b0 = a0 / 4;  // 2 draws per exchange, 8 per block
+        __syncthreads();                                // the previous chunk is applied
+        for (int b = threadIdx.x; b < (2 * m + 7) / 8; b += blockDim.x) {
+            const Philox4 r = philox4x64_10(kp.seed, kp.instance, uint64_t(b0 + b), uint64_t(p), uint64_t(t), purpose);
+            for (int i = 0; i < 8; ++i)
+                if (b * 8 + i < 2 * m) draws[b * 8 + i] = draw_from_block(r, i);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0)
+            for (int a = 0; a < m; ++a) {
+                const int i = int(scale_draw(draws[2 * a], uint32_t(n)));
+                const int j = int(scale_draw(draws[2 * a + 1], uint32_t(n)));
+                const uint16_t v = tour[i];
+                tour[i] = tour[j];
+                tour[j] = v;
+            }
     }
     __syncthreads();
 }
@@ -546,8 +578,9 @@ __device__ __forceinline__ void mut_keep_body(const Inst &I, int p)
 }
 
 // Mutation step 3: every particle not kept restarts from a Fisher-Yates
-// shuffle of stream (p, t, mut) with an empty velocity; its personal best
-// is kept and replaced only by a strictly cheaper shuffle.
+// shuffle of stream (p, t, mut), or with mutation_swaps = k > 0 is disturbed
+// by k random position exchanges from that stream, with an empty velocity;
+// its personal best is kept and replaced only by a strictly cheaper tour.
 __device__ __forceinline__ void mut_apply_body(const Inst &I, int p)
 {
     const int32_t *__restrict__ D = I.D;
@@ -562,7 +595,14 @@ __device__ __forceinline__ void mut_apply_body(const Inst &I, int p)
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int64_t redi[4];
     uint16_t *tour = reinterpret_cast<uint16_t *>(smem);
-    fisher_yates(tour, smem + size_t(st.ns) * 2, n, st.ns, kp, p, t, kMut);
+    if (kp.mutation_swaps > 0) {
+        const uint16_t *xg = st.X + size_t(p) * st.ns;
+        for (int k = threadIdx.x; k < n; k += blockDim.x) tour[k] = xg[k];
+        disturb(tour, reinterpret_cast<uint32_t *>(smem + size_t(st.ns) * 2), n, kp.mutation_swaps, kp, p, t,
+                kMut);
+    } else {
+        fisher_yates(tour, smem + size_t(st.ns) * 2, n, st.ns, kp, p, t, kMut);
+    }
     const int64_t cf = store_particle(D, st, p, tour, false, redi);
     const bool better = cf < st.FP[p];
     if (better)
@@ -670,7 +710,8 @@ DPSO_KERNELS(k_end, 64, end_body(I))
 // ---------------------------------------------------------------- launchers
 
 size_t init_lds_bytes(int ns) { return size_t(ns) * 2 + size_t(ns) * 14; }
-size_t mut_lds_bytes(int ns) { return size_t(ns) * 2 + size_t(ns) * 14; }
+// the tour, then the shuffle's work area or the disturbance's 2048 draws
+size_t mut_lds_bytes(int ns) { return size_t(ns) * 2 + std::max(size_t(ns) * 14, size_t(2048 * 4)); }
 
 namespace {
 

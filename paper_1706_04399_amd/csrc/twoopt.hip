@@ -14,6 +14,7 @@
 // (three row buffers in rotation), so each row of D is read from L2 once
 // per sweep.
 #include "device.hpp"
+#include "dpso.h"
 #include "kernels.hpp"
 
 namespace dpso {
@@ -457,15 +458,17 @@ hipError_t launch_class(int cls, const Inst *one, const Batch &B, int grid, int 
     case 7: return launch_wave<4, false>(one, B, grid, max_ns, s);
     case 8: return launch_wave<8, false>(one, B, grid, max_ns, s);
     case 9: return launch_wave<16, false>(one, B, grid, max_ns, s);
-    default: return launch_rows(one, B, grid, max_ns, s);
+    case 10: return launch_rows(one, B, grid, max_ns, s);
+    default: return launch_node_swap(one, B, grid, max_ns, s);
     }
 }
 
 }  // namespace
 
-int exchange_class(int n, const int32_t *D)
+int exchange_class(int n, const int32_t *D, int neighbourhood)
 {
-    if (n > 1024) return kExchangeClasses - 1;
+    if (neighbourhood == DPSO_NB_NODE_SWAP) return kExchangeClasses - 1;
+    if (n > 1024) return kExchangeClasses - 2;
     const bool vec4 = (n & 3) == 0 && (reinterpret_cast<uintptr_t>(D) & 15) == 0;
     const int mb = n <= 64 ? 0 : n <= 128 ? 1 : n <= 256 ? 2 : n <= 512 ? 3 : 4;
     return vec4 ? mb : 5 + mb;
@@ -473,7 +476,7 @@ int exchange_class(int n, const int32_t *D)
 
 hipError_t launch_2opt(const Inst &I, hipStream_t s)
 {
-    return launch_class(exchange_class(I.st.n, I.D), &I, Batch{}, I.st.S, I.st.ns, s);
+    return launch_class(exchange_class(I.st.n, I.D, I.kp.ee_neighbourhood), &I, Batch{}, I.st.S, I.st.ns, s);
 }
 
 hipError_t launch_batch_2opt(int cls, const Batch &items, int total, int max_ns, hipStream_t s)

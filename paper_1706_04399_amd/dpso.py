@@ -20,6 +20,7 @@ D_INF = (1 << 28) - 1
 MAX_N = 4096
 MAX_SWARM = 65536
 EE_OFF, EE_ON_STALL, EE_ALWAYS = 0, 1, 2
+NB_TWO_OPT, NB_NODE_SWAP = 0, 1
 
 
 class DpsoError(RuntimeError):
@@ -38,7 +39,8 @@ class Params(C.Structure):
                 ("w_q16", C.c_uint32), ("phi1_q16", C.c_uint32), ("phi2_q16", C.c_uint32),
                 ("mutation_period", C.c_int32), ("ee_trigger", C.c_int32),
                 ("ee_max_moves", C.c_int32), ("stall_limit", C.c_int32),
-                ("det_permille", C.c_int32), ("seed", C.c_uint64), ("instance", C.c_uint64)]
+                ("det_permille", C.c_int32), ("seed", C.c_uint64), ("instance", C.c_uint64),
+                ("ee_neighbourhood", C.c_int32), ("mutation_swaps", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -126,7 +128,9 @@ def _stream(stream):
 def _params(p) -> Params:
     if isinstance(p, Params):
         return p
-    return Params(**{k: int(p[k]) for k, _ in Params._fields_})
+    # fields added later (the exchange neighbourhood, the disturbance size)
+    # default to 0, their original behaviour
+    return Params(**{k: int(p.get(k, 0)) for k, _ in Params._fields_})
 
 
 def _dev(t: torch.Tensor, dtype) -> C.c_void_p:

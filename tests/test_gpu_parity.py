@@ -166,6 +166,42 @@ def test_largest_sizes(dp, n):
     lockstep(dp, D, prm, [1, 3], f"n{n}")
 
 
+NB = scenes.NB_NODE_SWAP
+VARIANTS = [
+    # (name, n, S, gens, overrides): node-swap exchange, disturbance mutation,
+    # conventional DPSO
+    ("swap_n2", 2, 5, 6, dict(ee_neighbourhood=NB, ee_trigger=2)),
+    ("swap_n3", 3, 4, 6, dict(ee_neighbourhood=NB, ee_trigger=2)),
+    ("swap_n4", 4, 7, 9, dict(ee_neighbourhood=NB, ee_trigger=2)),
+    ("swap_n5_S1_opt", 5, 1, 9, dict(ee_neighbourhood=NB, ee_trigger=2, ee_max_moves=0)),
+    ("swap_n40_stall", 40, 50, 12, dict(ee_neighbourhood=NB)),
+    ("swap_n65_opt", 65, 33, 9, dict(ee_neighbourhood=NB, ee_trigger=2, ee_max_moves=0)),
+    ("swap_n257", 257, 64, 6, dict(ee_neighbourhood=NB, ee_trigger=2)),
+    ("swap_n1030", 1030, 16, 3, dict(ee_neighbourhood=NB, ee_trigger=2)),
+    ("disturb_k1", 40, 50, 12, dict(mutation_swaps=1)),
+    ("disturb_k7", 65, 64, 9, dict(mutation_swaps=7, ee_trigger=2)),
+    ("disturb_k3000", 30, 20, 6, dict(mutation_swaps=3000)),      # several draw chunks
+    ("conventional", 50, 64, 20, dict(det_permille=0, mutation_period=0, ee_trigger=0)),
+    ("swap_and_disturb", 100, 64, 12, dict(ee_neighbourhood=NB, ee_trigger=2, mutation_swaps=4)),
+]
+
+
+@pytest.mark.parametrize("name,n,S,gens,kw", VARIANTS, ids=[v[0] for v in VARIANTS])
+def test_variants(dp, name, n, S, gens, kw):
+    sc = scenes.random_points(n, seed=3 * n + S, n_boxes=2 if n > 3 else 0)
+    D = oracle.build_dist(sc)
+    prm = scenes.swarm_params(S, gens, seed=23, instance=n, **kw)
+    lockstep(dp, D, prm, sorted({1, 2, 3, gens // 2 or 1, gens}), name)
+
+
+def test_node_swap_on_a_random_matrix(dp):
+    """Node-swap exchange to a local optimum on a non-metric matrix with many
+    equal entries (ties between exchanges)."""
+    D = scenes.random_dist(70, seed=8, max_mm=6)
+    prm = scenes.swarm_params(24, 6, seed=4, ee_neighbourhood=NB, ee_trigger=2, ee_max_moves=0)
+    lockstep(dp, D, prm, [1, 3, 6], "swap_ties")
+
+
 def test_collapsed_swarm_mutation(dp):
     """All particles identical at a mutation generation: one is kept."""
     n, S = 48, 96
@@ -249,6 +285,9 @@ BATCH = [
     (200, 20, {}), (257, 7, dict(ee_trigger=2)), (515, 6, dict(ee_trigger=2)),
     (1000, 5, dict(ee_trigger=2)), (1030, 3, dict(ee_trigger=2)),
     (50, 10, dict(stall_limit=2)), (40, 10, dict(ee_trigger=0)),
+    # paper-literal variants in the same batch as the default instances
+    (45, 10, dict(ee_neighbourhood=1, ee_trigger=2)), (2, 4, dict(ee_neighbourhood=1, ee_trigger=2)),
+    (301, 6, dict(ee_neighbourhood=1, ee_trigger=2, mutation_swaps=3)), (88, 12, dict(mutation_swaps=5)),
 ]
 
 
