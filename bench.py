@@ -212,6 +212,85 @@ def bench_serve(count: int, rate: float, warmup: int, budget_mb: int, plain: boo
     }
 
 
+ABLATION = [
+    # (name, overrides of the enhanced configuration)
+    ("DPSO (random init, no mutation, no exchange)", dict(det_permille=0, mutation_period=0, ee_trigger=0)),
+    ("+ initialization", dict(mutation_period=0, ee_trigger=0)),
+    ("+ random mutation", dict(ee_trigger=0)),
+    ("enhanced DPSO (+ 2-opt edge exchange)", dict()),
+    ("enhanced, node-swap exchange", dict(ee_neighbourhood=1)),
+    ("enhanced, mutation by disturbance", dict(mutation_swaps=-1)),   # -1: n / 10 exchanges
+]
+
+
+def bench_ablation(trials: int, generations: int):
+    """Effect of each augmentation, and enhanced vs conventional DPSO, on the
+    two synthetic stand-ins for the paper's datasets (facade n=30, bridge
+    girder n=200) with the paper's experiment settings (w = 1, phi1 = phi2 =
+    0.4, 100 particles, mutation every 3 generations, edge exchange when the
+    global best did not improve). Each variant runs `trials` seeds as one
+    batch; reported: final cost mean and std, the generation at which the
+    best cost was first reached, and the batch's wall time. Also times the
+    n=1000 benchmark workload with the node-swap neighbourhood against 2-opt."""
+    import numpy as np
+    import torch
+    from paper_1706_04399_amd import dpso, scenes
+
+    out = {"metric": "ablation", "unit": "mm", "trials": trials, "generations": generations,
+           "higher_is_better": False, "n_gpus": 1, "dtype": "int32", "data": "synthetic",
+           "settings": "w=1, phi1=phi2=0.4, swarm 100, mutation every 3 generations, exchange on stall",
+           "scenes": []}
+    stream = torch.cuda.Stream()
+    sc, _ = scenes.workload(1)                 # untimed: loads kernels, warms the allocator
+    warm = dpso.Batch([(dpso.build_dist(sc), scenes.swarm_params(100, 5))], stream=stream)
+    warm.init().run(5)
+    stream.synchronize()
+    for k, label in ((1, "building stand-in: facade n=30"), (2, "bridge stand-in: girder n=200")):
+        sc, _ = scenes.workload(k)
+        D = dpso.build_dist(sc)
+        rows = []
+        for name, kw in ABLATION:
+            kw = dict(kw)
+            if kw.get("mutation_swaps") == -1:
+                kw["mutation_swaps"] = max(2, sc.n // 10)
+            prm = [scenes.swarm_params(100, generations, w=1.0, phi1=0.4, phi2=0.4, seed=s,
+                                       instance=k, **kw) for s in range(trials)]
+            b = dpso.Batch([(D, p) for p in prm], stream=stream)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            b.init().run(generations)
+            stream.synchronize()
+            dt = time.perf_counter() - t0
+            costs, reach = [], []
+            for i in range(trials):
+                _, cost, _, trace = b.best(i)
+                costs.append(cost)
+                reach.append(int(np.argmax(trace == cost)))
+            rows.append({"variant": name, "cost_mean": round(float(np.mean(costs)), 1),
+                         "cost_std": round(float(np.std(costs)), 1),
+                         "reached_at_generation_mean": round(float(np.mean(reach)), 1),
+                         "seconds_for_all_trials": round(dt, 3), "params": kw})
+        base = rows[0]["cost_mean"]
+        for r in rows:
+            r["cost_improvement_vs_dpso_pct"] = round(100.0 * (base - r["cost_mean"]) / base, 2)
+        out["scenes"].append({"scene": label, "n": sc.n, "rows": rows})
+    # throughput of the two neighbourhoods on the benchmark workload
+    sc, prm3 = scenes.workload(3)
+    D = dpso.build_dist(sc)
+    thr = {}
+    for nb, name in ((0, "2-opt"), (1, "node swap")):
+        prm = dict(prm3, max_generations=25, ee_neighbourhood=nb)
+        st = dpso.init_nn(D, prm)
+        dpso.run(D, prm, st, 5)
+        torch.cuda.synchronize()
+        ph = dpso.run_profiled(D, prm, st, 20)
+        torch.cuda.synchronize()
+        thr[name] = {"particle_iters_per_s": round(prm["swarm_size"] * 20 / (ph["ms_total"] / 1e3), 1),
+                     "exchange_us_per_launch": round(ph["ms_exchange"] / ph["exchange_launches"] * 1e3, 1)}
+    out["throughput_n1000_swarm4096"] = thr
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -230,6 +309,9 @@ def main():
     ap.add_argument("--serve-warmup", type=int, default=200)
     ap.add_argument("--budget-mb", type=int, default=2048)
     ap.add_argument("--plain", action="store_true", help="serve one request at a time")
+    ap.add_argument("--ablation", type=int, default=0,
+                    help="run the augmentation ablation with this many trials per variant instead")
+    ap.add_argument("--ablation-generations", type=int, default=200)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (each swarm runs "
@@ -238,6 +320,9 @@ def main():
 
     if args.batch:
         print(json.dumps(bench_batch(args.batch, args.batch_generations)), flush=True)
+        return
+    if args.ablation:
+        print(json.dumps(bench_ablation(args.ablation, args.ablation_generations)), flush=True)
         return
     if args.serve:
         print(json.dumps(bench_serve(args.serve, args.rate, min(args.serve_warmup, args.serve // 4),
