@@ -36,7 +36,8 @@ class Params(C.Structure):
                 ("mutation_period", C.c_int32), ("ee_trigger", C.c_int32),
                 ("ee_max_moves", C.c_int32), ("stall_limit", C.c_int32),
                 ("det_permille", C.c_int32), ("seed", C.c_uint64), ("instance", C.c_uint64),
-                ("ee_neighbourhood", C.c_int32), ("mutation_swaps", C.c_int32)]
+                ("ee_neighbourhood", C.c_int32), ("mutation_swaps", C.c_int32),
+                ("velocity_cap", C.c_int32)]
 
 
 class _State(C.Structure):
@@ -76,6 +77,7 @@ def lib():
             "or_check_params": (i32, [P, i32]),
             "or_init": (i32, [P, P, P]),
             "or_move_core": (i32, [P, P, P, P, i32, i32, u32, u32, u32, u32, u32, P]),
+            "or_move_core_raw": (i32, [P, P, P, P, i32, i32, u32, u32, u32, u32, u32, i32, P]),
             "or_move_particle": (None, [P, P, P, i32, i32]),
             "or_mutation": (i32, [P, P, P, i32, P]),
             "or_generation": (i32, [P, P, P]),
@@ -306,6 +308,19 @@ def move_core(x, Pp, G, v, w_q16, phi1_q16, phi2_q16, u1, u2):
     y = np.zeros(n, np.int32)
     ln = lib().or_move_core(_p(x), _p(_i32(Pp)), _p(_i32(G)), _p(vv), len(v), n, w_q16,
                             phi1_q16, phi2_q16, u1, u2, _p(y))
+    return y, vv[:ln].copy()
+
+
+def move_core_raw(x, Pp, G, v, w_q16, phi1_q16, phi2_q16, u1, u2, cap):
+    """The move with the raw concatenated velocity truncated to `cap`."""
+    x = _i32(x)
+    n = len(x)
+    vv = np.zeros((max(n, 1), 2), np.int32)
+    v = _i32(v).reshape(-1, 2)
+    vv[: len(v)] = v
+    y = np.zeros(n, np.int32)
+    ln = lib().or_move_core_raw(_p(x), _p(_i32(Pp)), _p(_i32(G)), _p(vv), len(v), n, w_q16,
+                                phi1_q16, phi2_q16, u1, u2, cap, _p(y))
     return y, vv[:ln].copy()
 
 

@@ -36,6 +36,8 @@ typedef struct {
     uint64_t seed, instance;
     int32_t ee_neighbourhood; /* NB_TWO_OPT (segment reversal) or NB_NODE_SWAP   */
     int32_t mutation_swaps;   /* 0: reshuffle; k > 0: k random position exchanges */
+    int32_t velocity_cap;     /* 0: v <- y - x; c > 0: v <- the concatenation of
+                                 the three prefixes, its first c transpositions */
 } or_params;
 
 typedef struct {
@@ -400,6 +402,7 @@ int32_t or_check_params(const or_params *prm, int32_t n)
     if (prm->det_permille < 0 || prm->det_permille > 1000) return OR_EINVAL;
     if (prm->ee_neighbourhood < NB_TWO_OPT || prm->ee_neighbourhood > NB_NODE_SWAP) return OR_EINVAL;
     if (prm->mutation_swaps < 0 || prm->mutation_swaps > 65536) return OR_EINVAL;
+    if (prm->velocity_cap < 0 || prm->velocity_cap > n) return OR_EINVAL;
     return OR_OK;
 }
 
@@ -463,6 +466,31 @@ int32_t or_move_core(const int32_t *x, const int32_t *Pp, const int32_t *G, int3
     return lnew;
 }
 
+/* The same move with the velocity of eq. velocity kept as the raw
+ * concatenation w.v (+) phi1 r1.b (+) phi2 r2.c of the three applied prefixes
+ * (the operator (+) of Sect. 3.1) instead of being renormalised, truncated to
+ * its first `cap` transpositions (cap <= n, so v holds it). */
+int32_t or_move_core_raw(const int32_t *x, const int32_t *Pp, const int32_t *G, int32_t *v, int32_t lv,
+                         int32_t n, uint32_t w_q16, uint32_t phi1_q16, uint32_t phi2_q16, uint32_t u1,
+                         uint32_t u2, int32_t cap, int32_t *y)
+{
+    int32_t *b = malloc(sizeof(int32_t) * 2 * (size_t)(n > 0 ? n : 1));
+    int32_t *c = malloc(sizeof(int32_t) * 2 * (size_t)(n > 0 ? n : 1));
+    int32_t lb = or_bss(x, Pp, n, b);
+    int32_t lc = or_bss(x, G, n, c);
+    int32_t k[3];
+    or_truncate_counts(lv, lb, lc, w_q16, phi1_q16, phi2_q16, u1, u2, k);
+    memcpy(y, x, sizeof(int32_t) * (size_t)n);
+    or_apply_swaps(y, n, v, k[0]);
+    or_apply_swaps(y, n, b, k[1]);
+    or_apply_swaps(y, n, c, k[2]);
+    int32_t len = k[0] < cap ? k[0] : cap;   /* v already starts with its own prefix */
+    for (int32_t a = 0; a < k[1] && len < cap; a++, len++) { v[2 * len] = b[2 * a]; v[2 * len + 1] = b[2 * a + 1]; }
+    for (int32_t a = 0; a < k[2] && len < cap; a++, len++) { v[2 * len] = c[2 * a]; v[2 * len + 1] = c[2 * a + 1]; }
+    free(b); free(c);
+    return len;
+}
+
 /* Move of particle p at generation t: r1, r2 are the first two draws of the
  * particle's velocity stream for generation t; the personal best follows
  * when the new cost is strictly lower. */
@@ -474,8 +502,13 @@ void or_move_particle(const int32_t *D, const or_params *prm, or_state *st, int3
     or_stream s;
     stream_open(&s, prm->seed, prm->instance, (uint64_t)p, (uint64_t)t, PURPOSE_VEL);
     uint32_t u1 = stream_next(&s), u2 = stream_next(&s);
-    st->VL[p] = or_move_core(x, row32(st->P, n, p), st->G, st->V + (int64_t)p * n * 2, st->VL[p], n,
-                             prm->w_q16, prm->phi1_q16, prm->phi2_q16, u1, u2, y);
+    int32_t *v = st->V + (int64_t)p * n * 2;
+    if (prm->velocity_cap > 0)
+        st->VL[p] = or_move_core_raw(x, row32(st->P, n, p), st->G, v, st->VL[p], n, prm->w_q16,
+                                     prm->phi1_q16, prm->phi2_q16, u1, u2, prm->velocity_cap, y);
+    else
+        st->VL[p] = or_move_core(x, row32(st->P, n, p), st->G, v, st->VL[p], n, prm->w_q16,
+                                 prm->phi1_q16, prm->phi2_q16, u1, u2, y);
     memcpy(x, y, sizeof(int32_t) * (size_t)n);
     st->F[p] = or_tour_cost(D, n, x);
     pbest_rule(st, p);

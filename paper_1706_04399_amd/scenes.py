@@ -214,14 +214,15 @@ NB_TWO_OPT, NB_NODE_SWAP = 0, 1          # edge-exchange neighbourhoods
 def swarm_params(swarm_size, max_generations, *, w=0.7, phi1=1.5, phi2=1.5,
                  mutation_period=3, ee_trigger=EE_ON_STALL, ee_max_moves=1,
                  stall_limit=0, det_permille=100, seed=0, instance=0,
-                 ee_neighbourhood=NB_TWO_OPT, mutation_swaps=0) -> dict:
+                 ee_neighbourhood=NB_TWO_OPT, mutation_swaps=0, velocity_cap=0) -> dict:
     return dict(swarm_size=int(swarm_size), max_generations=int(max_generations),
                 w_q16=int(round(w * Q16)), phi1_q16=int(round(phi1 * Q16)),
                 phi2_q16=int(round(phi2 * Q16)), mutation_period=int(mutation_period),
                 ee_trigger=int(ee_trigger), ee_max_moves=int(ee_max_moves),
                 stall_limit=int(stall_limit), det_permille=int(det_permille),
                 seed=int(seed), instance=int(instance),
-                ee_neighbourhood=int(ee_neighbourhood), mutation_swaps=int(mutation_swaps))
+                ee_neighbourhood=int(ee_neighbourhood), mutation_swaps=int(mutation_swaps),
+                velocity_cap=int(velocity_cap))
 
 
 def workload(k: int):

@@ -1,7 +1,8 @@
 """Pins of the oracle's paper-literal variants: the node-swap exchange
 neighbourhood (the edge-exchange kernel and pseudo code of Sect. 3.3 exchange
-two nodes and keep the best) and mutation as a disturbance by random position
-exchanges (the mutation text of Sect. 3.2.2)."""
+two nodes and keep the best), mutation as a disturbance by random position
+exchanges (the mutation text of Sect. 3.2.2) and the velocity kept as the raw
+concatenation of eq. velocity with a length cap."""
 import itertools
 
 import numpy as np
@@ -160,3 +161,61 @@ def test_variant_params_are_checked(orc):
     for bad in (dict(ee_neighbourhood=2), dict(ee_neighbourhood=-1), dict(mutation_swaps=-1),
                 dict(mutation_swaps=65537)):
         assert orc.check_params(dict(base, **bad), 10) != 0
+
+
+# ----------------------------------------------- raw concatenated velocity
+
+def _golden_move(name):
+    from conftest import golden_lines
+    g = {row[0]: [int(v) for v in row[1:]] for row in golden_lines(name)}
+    return g
+
+
+def test_raw_velocity_worked_example(orc):
+    g = _golden_move("move_step_raw.txt")
+    w, p1, p2 = g["coef"]
+    u1, u2 = g["draws"]
+    for cap in (5, 4, 3, 1):
+        y, v = orc.move_core_raw(g["x"], g["P"], g["G"], np.array(g["v"]).reshape(-1, 2), w, p1, p2,
+                                 u1, u2, cap)
+        assert y.tolist() == g["y"]
+        assert v.reshape(-1).tolist() == g["vnew"][: 2 * cap]
+
+
+def test_raw_velocity_properties(orc):
+    """Same position as the renormalised move; the uncapped list applied to x
+    gives y; a smaller cap keeps a prefix of the list."""
+    rng = np.random.default_rng(11)
+    for trial in range(200):
+        n = int(rng.integers(2, 30))
+        x, P, G = rng.permutation(n), rng.permutation(n), rng.permutation(n)
+        v = orc.bss(rng.permutation(n), rng.permutation(n))
+        w, p1, p2 = (int(c) for c in rng.integers(0, 131073, size=3))
+        u1, u2 = (int(d) for d in rng.integers(0, 2**32, size=2))
+        y0, _ = orc.move_core(x, P, G, v, w, p1, p2, u1, u2)
+        y, full = orc.move_core_raw(x, P, G, v, w, p1, p2, u1, u2, n)
+        assert (y == y0).all()
+        if len(full) < n:                       # the cap did not cut the list
+            assert (orc.apply_swaps(x, full) == y).all()
+        cap = int(rng.integers(1, n + 1))
+        _, short = orc.move_core_raw(x, P, G, v, w, p1, p2, u1, u2, cap)
+        assert len(short) == min(cap, len(full)) and (short == full[: len(short)]).all()
+
+
+def test_raw_velocity_runs_keep_the_invariants(orc):
+    sc = scenes.random_points(24, seed=6, n_boxes=2)
+    D = orc.build_dist(sc)
+    prm = scenes.swarm_params(40, 30, seed=3, w=1.0, phi1=0.4, phi2=0.4, velocity_cap=20)
+    st = orc.new_state(D, prm)
+    prev = st.copy()
+    grew = False
+    for t in range(1, 31):
+        orc.generation(D, prm, st)
+        check_state(D, st)
+        assert (st.VL <= 20).all()
+        grew |= bool((st.VL > 0).any())
+        assert st.FG <= prev.FG
+        prev = st.copy()
+    assert grew
+    for bad in (-1, 25):
+        assert orc.check_params(dict(prm, velocity_cap=bad), 24) != 0
