@@ -220,6 +220,7 @@ ABLATION = [
     ("enhanced DPSO (+ 2-opt edge exchange)", dict()),
     ("enhanced, node-swap exchange", dict(ee_neighbourhood=1)),
     ("enhanced, mutation by disturbance", dict(mutation_swaps=-1)),   # -1: n / 10 exchanges
+    ("enhanced, raw concatenated velocity", dict(velocity_cap=-1)),   # -1: capped at n
 ]
 
 
@@ -253,6 +254,8 @@ def bench_ablation(trials: int, generations: int):
             kw = dict(kw)
             if kw.get("mutation_swaps") == -1:
                 kw["mutation_swaps"] = max(2, sc.n // 10)
+            if kw.get("velocity_cap") == -1:
+                kw["velocity_cap"] = sc.n
             prm = [scenes.swarm_params(100, generations, w=1.0, phi1=0.4, phi2=0.4, seed=s,
                                        instance=k, **kw) for s in range(trials)]
             b = dpso.Batch([(D, p) for p in prm], stream=stream)

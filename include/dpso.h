@@ -99,6 +99,11 @@ typedef struct {
     int32_t mutation_swaps;  /* 0: mutated particles restart from a shuffle; k > 0
                                 (at most 65536): they are disturbed by k exchanges of
                                 random positions instead (mutation text, Sect. 3.2.2) */
+    int32_t velocity_cap;    /* 0: the velocity is renormalised to y - x after each
+                                move; c in 1..n: it is kept as the raw concatenation
+                                of eq. velocity (operator (+), Sect. 3.1), truncated to
+                                its first c transpositions. A state keeps the mode it
+                                was initialised with (another mode: DPSO_E_STATE).  */
 } dpso_params;
 
 /* Progress of a swarm, read by dpso_get_info. */

@@ -63,6 +63,8 @@ dpso_status check_params(const dpso_params *p, int32_t n)
         return fail(DPSO_E_INVAL, "ee_neighbourhood = %d is not a DPSO_NB_* value", p->ee_neighbourhood);
     if (p->mutation_swaps < 0 || p->mutation_swaps > 65536)
         return fail(DPSO_E_INVAL, "mutation_swaps = %d outside 0..65536", p->mutation_swaps);
+    if (p->velocity_cap < 0 || p->velocity_cap > n)
+        return fail(DPSO_E_INVAL, "velocity_cap = %d outside 0..n = %d", p->velocity_cap, n);
     return DPSO_OK;
 }
 
@@ -83,6 +85,7 @@ dpso::KParams kernel_params(const dpso_params *p)
     k.det_count = int32_t(m < p->swarm_size ? m : p->swarm_size);
     k.ee_neighbourhood = p->ee_neighbourhood;
     k.mutation_swaps = p->mutation_swaps;
+    k.velocity_cap = p->velocity_cap;
     return k;
 }
 
@@ -107,7 +110,8 @@ dpso_status read_header(const void *d_state, dpso::Hdr *h, hipStream_t s)
     if (h->magic != dpso::kMagic || h->n < 1 || h->n > DPSO_MAX_N || h->S < 1 ||
         h->S > DPSO_MAX_SWARM || h->cap < 1)
         return fail(DPSO_E_STATE, "state buffer is not an initialised swarm");
-    if (h->err) return fail(DPSO_E_STATE, "state rejected by dpso_run: it does not match n / swarm_size");
+    if (h->err)
+        return fail(DPSO_E_STATE, "state rejected by dpso_run: it does not match n / swarm_size / velocity mode");
     return DPSO_OK;
 }
 
@@ -523,7 +527,12 @@ dpso_status dpso_export_state(const void *d_state, int32_t n, int32_t swarm_size
         uint16_t *row = out->V + p * size_t(n) * 2;
         std::fill(row, row + size_t(n) * 2, uint16_t(0));
         const uint16_t *from = vt.data() + p * 2 * L.ns;
-        out->vlen[p] = has_v[p] ? host_difference(from, from + L.ns, n, row, cur, pos) : 0;
+        if (h.velocity_cap > 0) {  // a transposition list, held as it is
+            out->vlen[p] = has_v[p];
+            std::copy(from, from + 2 * size_t(has_v[p]), row);
+        } else {
+            out->vlen[p] = has_v[p] ? host_difference(from, from + L.ns, n, row, cur, pos) : 0;
+        }
     }
     out->generation = h.t;
     out->stall = h.stall;
@@ -561,15 +570,24 @@ dpso_status dpso_import_state(void *d_state, size_t state_bytes, int32_t n, int3
     for (size_t p = 0; p < S; ++p) {
         if (!is_perm(in->X + p * n) || !is_perm(in->P + p * n))
             return fail(DPSO_E_INVAL, "tour of particle %zu is not a permutation", p);
-        if (in->vlen[p] < 0 || in->vlen[p] > n - 1)
+        const int32_t most = h.velocity_cap > 0 ? h.velocity_cap : n - 1;
+        if (in->vlen[p] < 0 || in->vlen[p] > most)
             return fail(DPSO_E_INVAL, "velocity length of particle %zu out of range", p);
     }
     std::vector<uint16_t> vt(S * 2 * size_t(L.ns), 0);
     std::vector<int32_t> has_v(S);
     for (size_t p = 0; p < S; ++p) {
-        has_v[p] = in->vlen[p] > 0;
+        const uint16_t *pairs = in->V + p * size_t(n) * 2;
         uint16_t *from = vt.data() + p * 2 * L.ns;
-        if (has_v[p] && !host_velocity_tours(in->V + p * size_t(n) * 2, in->vlen[p], n, from, from + L.ns))
+        if (h.velocity_cap > 0) {  // raw velocity: any list of labels
+            for (int32_t k = 0; k < 2 * in->vlen[p]; ++k)
+                if (pairs[k] >= n) return fail(DPSO_E_INVAL, "velocity of particle %zu names a label >= n", p);
+            std::copy(pairs, pairs + 2 * size_t(in->vlen[p]), from);
+            has_v[p] = in->vlen[p];
+            continue;
+        }
+        has_v[p] = in->vlen[p] > 0;
+        if (has_v[p] && !host_velocity_tours(pairs, in->vlen[p], n, from, from + L.ns))
             return fail(DPSO_E_INVAL, "velocity of particle %zu is not a canonical difference of two tours", p);
     }
     if (!is_perm(in->G)) return fail(DPSO_E_INVAL, "global best is not a permutation");

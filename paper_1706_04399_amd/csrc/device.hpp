@@ -17,7 +17,7 @@ struct Philox4 {
     uint64_t w0, w1, w2, w3;
 };
 
-__device__ inline Philox4 philox4x64_10(uint64_t k0, uint64_t k1, uint64_t x0, uint64_t x1,
+__device__ __forceinline__ Philox4 philox4x64_10(uint64_t k0, uint64_t k1, uint64_t x0, uint64_t x1,
                                         uint64_t x2, uint64_t x3)
 {
     constexpr uint64_t kMulA = 0xD2E7470EE14C6C93ull;

@@ -5,8 +5,10 @@
 //   X, P   uint16 [S][ns]   current and personal-best tours (ns = n rounded up
 //                           to 64 labels, so each row starts 128-byte aligned)
 //   V      uint16 [S][2][ns] velocity as the pair of tours (from, to) whose
-//                           canonical difference to - from is the velocity
+//                           canonical difference to - from is the velocity, or
+//                           (raw velocity) up to ns transpositions (a, b)
 //   VL     int32  [S]       1 if particle p has a velocity, 0 if it is empty
+//                           (raw velocity: the number of transpositions)
 //   F, FP  int64  [S]       costs of X and P
 //   G      uint16 [ns]      global-best tour
 //   trace  int64  [cap]     global-best cost after each generation
@@ -31,6 +33,7 @@ struct Hdr {
     int32_t ee_ran;    // edge exchange runs in the current generation
     int32_t err;       // non-zero: state rejected by a kernel
     int32_t max_generations, stall_limit;
+    int32_t velocity_cap;  // 0: velocity held as two tours; > 0: as a transposition list
     int64_t FG;        // cost of the global best
     uint64_t n_sweeps, n_moves, n_reshuffled;
 };
@@ -99,7 +102,7 @@ struct KParams {
     uint32_t w_q16, phi1_q16, phi2_q16;
     int32_t mutation_period, ee_trigger, ee_max_moves, stall_limit, max_generations;
     int32_t det_count;  // number of nearest-neighbour seeded particles
-    int32_t ee_neighbourhood, mutation_swaps;
+    int32_t ee_neighbourhood, mutation_swaps, velocity_cap;
 };
 
 // One swarm as the kernels see it: its distance matrix, state and params.

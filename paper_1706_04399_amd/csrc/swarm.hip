@@ -161,6 +161,7 @@ __device__ __forceinline__ void hdr_init_body(const Inst &I)
     h->err = 0;
     h->max_generations = max_generations;
     h->stall_limit = stall_limit;
+    h->velocity_cap = I.kp.velocity_cap;
     h->FG = 0;
     h->n_sweeps = h->n_moves = h->n_reshuffled = 0;
 }
@@ -169,7 +170,9 @@ __device__ __forceinline__ void hdr_init_body(const Inst &I)
 __device__ __forceinline__ void hdr_check_body(const Inst &I)
 {
     Hdr *h = I.st.hdr;
-    if (h->magic != kMagic || h->n != I.st.n || h->S != I.st.S || h->cap != I.cap) h->err = 1;
+    if (h->magic != kMagic || h->n != I.st.n || h->S != I.st.S || h->cap != I.cap ||
+        (h->velocity_cap > 0) != (I.kp.velocity_cap > 0))
+        h->err = 1;
 }
 
 // One workgroup per particle. Particles below det_count take the
@@ -434,6 +437,118 @@ __device__ inline int prefix_count(uint64_t coef_q16, uint64_t r16, int len)
 
 size_t move_lds_bytes(int ns) { return size_t(ns) * 2 * 8 + size_t(ns) * 4 * 2 + 64; }  // + sums, votes
 
+// The move with the velocity kept as the raw concatenation of eq. velocity
+// (velocity_cap > 0): y as in the default move, and the new velocity is the
+// list of the transpositions applied, in order (the stored velocity's
+// prefix, then the prefixes of P - x and G - x), truncated to velocity_cap.
+// The lists are walked in order, so one lane does the walking: wave 0 stages
+// the tours in LDS, lane 0 applies the stored prefix, counts the cycles of
+// each difference (its length is n minus that count) and scans the canonical
+// difference up to its prefix length, appending and applying each emitted
+// transposition; the other waves leave at once (no workgroup barrier here).
+__device__ __forceinline__ void move_raw_body(const Inst &I, int part)
+{
+    if (threadIdx.x >= 64) return;
+    const int32_t *__restrict__ D = I.D;
+    const View st = I.st;
+    const KParams kp = I.kp;
+    const int t = st.hdr->t + 1;
+    const int n = st.n, ns = st.ns, lane = threadIdx.x;
+    extern __shared__ __align__(16) unsigned char smem[];
+    uint16_t *y = reinterpret_cast<uint16_t *>(smem);  // 15 ns bytes in all
+    uint16_t *posy = y + ns, *cur = posy + ns, *posc = cur + ns, *T = posc + ns;
+    uint8_t *seen = reinterpret_cast<uint8_t *>(T + ns);
+    uint16_t *lst = reinterpret_cast<uint16_t *>(seen + ns);  // ns transpositions
+    const uint16_t *xg = st.X + size_t(part) * ns;
+    uint16_t *vg = st.V + size_t(part) * 2 * ns;
+    const int lv = st.VL[part];
+    const uint64_t w0 = philox4x64_10(kp.seed, kp.instance, 0, uint64_t(part), uint64_t(t), kVel).w0;
+    const uint64_t rr[2] = {uint32_t(w0) >> 16, uint32_t(w0 >> 32) >> 16};
+    const uint32_t coef[2] = {kp.phi1_q16, kp.phi2_q16};
+    const uint16_t *targets[2] = {st.P + size_t(part) * ns, st.G};
+    for (int k = lane; k < n; k += 64) {
+        const uint16_t v = xg[k];
+        y[k] = v;
+        posy[v] = uint16_t(k);
+    }
+    for (int k = lane; k < 2 * lv; k += 64) lst[k] = vg[k];
+    int len = 0;
+    for (int d = 0; d < 2; ++d) {
+        for (int k = lane; k < n; k += 64) {  // cur <- x, T <- P or G
+            const uint16_t v = xg[k];
+            cur[k] = v;
+            posc[v] = uint16_t(k);
+            T[k] = targets[d][k];
+            seen[k] = 0;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (lane == 0) {
+            if (d == 0) {  // the stored velocity's prefix
+                const uint64_t kw = (uint64_t(kp.w_q16) * uint64_t(lv)) >> 16;
+                len = kw < uint64_t(lv) ? int(kw) : lv;
+                for (int a = 0; a < len; ++a) {
+                    const uint16_t la = lst[2 * a], lb = lst[2 * a + 1];
+                    const uint16_t i = posy[la], j = posy[lb];
+                    y[i] = lb;
+                    y[j] = la;
+                    posy[la] = j;
+                    posy[lb] = i;
+                }
+                len = min(len, kp.velocity_cap);
+            }
+            int cycles = 0;  // of rho(q) = position in x of T[q]
+            for (int q = 0; q < n; ++q) {
+                if (seen[q]) continue;
+                ++cycles;
+                for (int r = q; !seen[r]; r = posc[T[r]]) seen[r] = 1;
+            }
+            const int k = prefix_count(coef[d], rr[d], n - cycles);
+            for (int q = 0, e = 0; e < k; ++q) {
+                const uint16_t la = cur[q], lb = T[q];
+                if (la == lb) continue;
+                const uint16_t j = posc[lb];  // cur: exchange labels la (at q) and lb
+                cur[q] = lb;
+                cur[j] = la;
+                posc[lb] = uint16_t(q);
+                posc[la] = j;
+                const uint16_t yi = posy[la], yj = posy[lb];  // the same exchange on y
+                y[yi] = lb;
+                y[yj] = la;
+                posy[la] = yj;
+                posy[lb] = yi;
+                if (len < kp.velocity_cap) {
+                    lst[2 * len] = la;
+                    lst[2 * len + 1] = lb;
+                    ++len;
+                }
+                ++e;
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    len = __shfl(len, 0, 64);
+    uint16_t *xo = st.X + size_t(part) * ns;
+    int64_t c = 0;
+    for (int k = lane; k < n; k += 64) {
+        xo[k] = y[k];
+        c += D[size_t(y[k]) * n + y[k + 1 < n ? k + 1 : 0]];
+    }
+    for (int k = lane; k < 2 * len; k += 64) vg[k] = lst[k];
+    c = wave_sum_i64(c);
+    const bool better = c < st.FP[part];
+    if (better)
+        for (int k = lane; k < n; k += 64) st.P[size_t(part) * ns + k] = y[k];
+    if (lane == 0) {
+        st.F[part] = c;
+        st.VL[part] = len;
+        if (better) st.FP[part] = c;
+    }
+}
+
 template <int EPT>
 __device__ __forceinline__ void move_body(const Inst &I, int part)
 {
@@ -442,6 +557,10 @@ __device__ __forceinline__ void move_body(const Inst &I, int part)
     const KParams kp = I.kp;
     const Hdr *h = st.hdr;
     if (h->err || h->done) return;
+    if (kp.velocity_cap > 0) {  // uniform over the workgroup
+        move_raw_body(I, part);
+        return;
+    }
     const int t = h->t + 1;
     const int n = st.n, ns = st.ns, tid = threadIdx.x;
     extern __shared__ __align__(16) unsigned char smem[];

@@ -40,7 +40,8 @@ class Params(C.Structure):
                 ("mutation_period", C.c_int32), ("ee_trigger", C.c_int32),
                 ("ee_max_moves", C.c_int32), ("stall_limit", C.c_int32),
                 ("det_permille", C.c_int32), ("seed", C.c_uint64), ("instance", C.c_uint64),
-                ("ee_neighbourhood", C.c_int32), ("mutation_swaps", C.c_int32)]
+                ("ee_neighbourhood", C.c_int32), ("mutation_swaps", C.c_int32),
+                ("velocity_cap", C.c_int32)]
 
 
 class Info(C.Structure):

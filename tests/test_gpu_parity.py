@@ -183,6 +183,13 @@ VARIANTS = [
     ("disturb_k3000", 30, 20, 6, dict(mutation_swaps=3000)),      # several draw chunks
     ("conventional", 50, 64, 20, dict(det_permille=0, mutation_period=0, ee_trigger=0)),
     ("swap_and_disturb", 100, 64, 12, dict(ee_neighbourhood=NB, ee_trigger=2, mutation_swaps=4)),
+    # velocity kept as the raw concatenation, with a cap
+    ("raw_cap_n", 40, 50, 12, dict(velocity_cap=40)),
+    ("raw_cap_10", 65, 33, 9, dict(velocity_cap=10, w=1.0, phi1=0.4, phi2=0.4)),
+    ("raw_n1", 1, 3, 4, dict(velocity_cap=1)),
+    ("raw_n1030", 1030, 16, 3, dict(velocity_cap=500, ee_trigger=2)),
+    ("raw_all_variants", 100, 64, 12, dict(velocity_cap=60, ee_neighbourhood=NB, mutation_swaps=3,
+                                           ee_trigger=2)),
 ]
 
 
@@ -200,6 +207,32 @@ def test_node_swap_on_a_random_matrix(dp):
     D = scenes.random_dist(70, seed=8, max_mm=6)
     prm = scenes.swarm_params(24, 6, seed=4, ee_neighbourhood=NB, ee_trigger=2, ee_max_moves=0)
     lockstep(dp, D, prm, [1, 3, 6], "swap_ties")
+
+
+def test_raw_velocity_import_and_mode_check(dp):
+    """Arbitrary transposition lists imported into a raw-velocity state move
+    the swarm exactly as in the oracle; a state is refused by a run in the
+    other velocity mode."""
+    n, S = 36, 20
+    D = oracle.build_dist(scenes.random_points(n, seed=12, n_boxes=2))
+    prm = scenes.swarm_params(S, 20, seed=6, velocity_cap=25, w=1.0)
+    st = synthetic_state(D, prm, t=4, seed=31)
+    rng = np.random.default_rng(5)
+    st.VL[:] = rng.integers(0, 26, size=S)
+    st.V[:] = rng.integers(0, n, size=st.V.shape)       # any labels, any order
+    Dg = _dev(D)
+    state = dp.init_nn(Dg, prm)
+    dp.import_state(state, n, S, as_host(st))
+    assert not mismatches(dp.export_state(state, n, S), st)
+    note("raw velocity: generation 5 from an imported state")
+    dp.run(Dg, prm, state, 2)
+    oracle.run(D, prm, st, 2)
+    bad = mismatches(dp.export_state(state, n, S), st)
+    assert not bad, bad
+    with pytest.raises(dp.DpsoError) as ei:
+        dp.run(Dg, dict(prm, velocity_cap=0), state, 1)
+        dp.get_info(state)
+    assert ei.value.status == dp.E_STATE
 
 
 def test_collapsed_swarm_mutation(dp):
@@ -288,6 +321,7 @@ BATCH = [
     # paper-literal variants in the same batch as the default instances
     (45, 10, dict(ee_neighbourhood=1, ee_trigger=2)), (2, 4, dict(ee_neighbourhood=1, ee_trigger=2)),
     (301, 6, dict(ee_neighbourhood=1, ee_trigger=2, mutation_swaps=3)), (88, 12, dict(mutation_swaps=5)),
+    (77, 9, dict(velocity_cap=30, w=1.0, phi1=0.4, phi2=0.4)),
 ]
 
 

@@ -48,13 +48,14 @@ def _params(**kw):
 
 def test_validation_errors(dp):
     dp.validate_params(_params(), 30)
-    dp.validate_params(_params(ee_neighbourhood=1, mutation_swaps=65536), 30)
+    dp.validate_params(_params(ee_neighbourhood=1, mutation_swaps=65536, velocity_cap=30), 30)
     bad = [(dict(swarm_size=0), 30, dp.E_INVAL), (dict(swarm_size=65537), 30, dp.E_INVAL),
            (dict(w_q16=131073), 30, dp.E_INVAL), (dict(ee_trigger=3), 30, dp.E_INVAL),
            (dict(det_permille=1001), 30, dp.E_INVAL), (dict(mutation_period=-1), 30, dp.E_INVAL),
            (dict(ee_max_moves=-1), 30, dp.E_INVAL), (dict(), 0, dp.E_INVAL),
            (dict(ee_neighbourhood=2), 30, dp.E_INVAL), (dict(ee_neighbourhood=-1), 30, dp.E_INVAL),
            (dict(mutation_swaps=-1), 30, dp.E_INVAL), (dict(mutation_swaps=65537), 30, dp.E_INVAL),
+           (dict(velocity_cap=-1), 30, dp.E_INVAL), (dict(velocity_cap=31), 30, dp.E_INVAL),
            (dict(), dp.MAX_N + 1, dp.E_RANGE)]
     for kw, n, code in bad:
         p = _params()
