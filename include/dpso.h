@@ -150,6 +150,41 @@ dpso_status dpso_validate_params(const dpso_params *params, int32_t n);
  * used by the generation loop: dpso_run allocates nothing. */
 size_t dpso_state_bytes(int32_t n, int32_t swarm_size, int32_t max_generations);
 
+/* A planar surface to inspect (Sect. 2.1): an axis-aligned rectangle in the
+ * plane {coordinate normal_axis = lo_mm[normal_axis]} spanning lo..hi along
+ * the two other axes (lo_mm[normal_axis] == hi_mm[normal_axis]); the UAV
+ * views it from the side normal_sign (+1 or -1) of the plane. */
+typedef struct {
+    int32_t lo_mm[3], hi_mm[3];
+    int32_t normal_axis;  /* 0, 1, 2 = x, y, z */
+    int32_t normal_sign;  /* +1 or -1           */
+} dpso_surface;
+
+/* Camera and image requirements of the viewpoint selection (Sect. 2.1). */
+typedef struct {
+    int32_t resolution_px;    /* r_c: pixels along the image side          */
+    int32_t feature_um;       /* s_f: smallest feature to resolve          */
+    int32_t overlap_permille; /* o_p: overlap of neighbouring images, 0..999 */
+    int32_t focal_um;         /* f: focal length                           */
+    int32_t sensor_um;        /* s_s: sensor size along the same side       */
+} dpso_camera;
+
+/* Viewpoint selection (Sect. 2.1, eq. fov, eq. premitive, eq.
+ * cameraDistance): footprint a = r_c s_f / 2, cell size p = (1 - o_p) a,
+ * working distance d = a f / s_s (exact in um, then truncated to whole um).
+ * Each surface is covered by a grid of cells of size p anchored at its low
+ * corner, max(1, ceil(L / p)) cells along each in-plane axis of extent L (the
+ * last cell may overhang); each cell centre moved d along the viewing side
+ * is one viewpoint, its coordinates rounded half up to whole mm. Order:
+ * surface by surface, the lower in-plane axis outer, the other inner. Host
+ * function (no device work). *n_out receives the number of viewpoints; with
+ * vp_mm == NULL nothing else happens (counting). Otherwise the viewpoints are
+ * written to vp_mm (host [max_n][3]) if they fit, else nothing is written
+ * and DPSO_E_RANGE is returned (also for a coordinate outside int32).
+ * DPSO_E_INVAL for a malformed surface or camera (a cell size below 1 um). */
+dpso_status dpso_viewpoints(const dpso_surface *surfaces, int32_t count, const dpso_camera *camera,
+                            int32_t *vp_mm, int32_t max_n, int32_t *n_out);
+
 /* Bytes of device workspace dpso_build_dist needs for this scene size. */
 size_t dpso_dist_work_bytes(int32_t n, int32_t n_boxes);
 

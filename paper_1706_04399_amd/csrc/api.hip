@@ -9,11 +9,14 @@
 #include <vector>
 
 #include "dpso.h"
+#include "errors.hpp"
 #include "kernels.hpp"
 
-namespace {
+namespace dpso {
 
+namespace {
 thread_local char g_error[512] = "";
+}
 
 dpso_status fail(dpso_status code, const char *fmt, ...)
 {
@@ -29,6 +32,15 @@ dpso_status ok()
     g_error[0] = 0;
     return DPSO_OK;
 }
+
+const char *last_error() { return g_error; }
+
+}  // namespace dpso
+
+using dpso::fail;
+using dpso::ok;
+
+namespace {
 
 dpso_status hip_fail(hipError_t e, const char *what)
 {
@@ -224,8 +236,8 @@ dpso_status plan_batch(const dpso_batch_item *items, int32_t count, void *d_work
         const dpso_batch_item &it = items[i];
         dpso_status st = check_params(&it.params, it.n);
         if (st) {
-            char why[sizeof g_error];
-            strncpy(why, g_error, sizeof why);
+            char why[512];
+            strncpy(why, dpso::last_error(), sizeof why);
             why[sizeof why - 1] = 0;
             return fail(st, "item %d: %s", i, why);
         }
@@ -365,7 +377,7 @@ extern "C" {
 
 const char *dpso_version(void) { return "dpso-mi355x 0.1 (gfx950)"; }
 
-const char *dpso_last_error(void) { return g_error; }
+const char *dpso_last_error(void) { return dpso::last_error(); }
 
 dpso_status dpso_validate_params(const dpso_params *params, int32_t n)
 {

@@ -34,6 +34,16 @@ class Scene(C.Structure):
                 ("n_boxes", C.c_int32), ("clearance_mm", C.c_int32)]
 
 
+class Surface(C.Structure):
+    _fields_ = [("lo_mm", C.c_int32 * 3), ("hi_mm", C.c_int32 * 3), ("normal_axis", C.c_int32),
+                ("normal_sign", C.c_int32)]
+
+
+class Camera(C.Structure):
+    _fields_ = [("resolution_px", C.c_int32), ("feature_um", C.c_int32),
+                ("overlap_permille", C.c_int32), ("focal_um", C.c_int32), ("sensor_um", C.c_int32)]
+
+
 class Params(C.Structure):
     _fields_ = [("swarm_size", C.c_int32), ("max_generations", C.c_int32),
                 ("w_q16", C.c_uint32), ("phi1_q16", C.c_uint32), ("phi2_q16", C.c_uint32),
@@ -92,6 +102,8 @@ EXPORTS = {
     "dpso_export_state": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p]),
     "dpso_import_state": (C.c_int32, [C.c_void_p, C.c_size_t, C.c_int32, C.c_int32, C.c_void_p,
                                       C.c_void_p]),
+    "dpso_viewpoints": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32,
+                                    C.c_void_p]),
 }
 
 _lib = None
@@ -221,6 +233,23 @@ def get_best(state: torch.Tensor, stream=None):
     _check(lib().dpso_get_best(_dev(state, torch.uint8), tour.ctypes.data, C.byref(cost),
                                C.byref(gen), trace.ctypes.data, _stream(stream)))
     return tour, cost.value, gen.value, trace[: gen.value + 1]
+
+
+def viewpoints(surfaces, camera: dict) -> np.ndarray:
+    """Viewpoints (int32 [n][3] mm) covering the surfaces: each surface is a
+    dict with lo_mm, hi_mm (3 ints), normal_axis and normal_sign; camera has
+    the fields of dpso_camera. Host computation."""
+    arr = (Surface * max(len(surfaces), 1))()
+    for k, f in enumerate(surfaces):
+        arr[k] = Surface((C.c_int32 * 3)(*f["lo_mm"]), (C.c_int32 * 3)(*f["hi_mm"]),
+                         int(f["normal_axis"]), int(f["normal_sign"]))
+    cam = Camera(**{k: int(camera[k]) for k, _ in Camera._fields_})
+    count = C.c_int32()
+    _check(lib().dpso_viewpoints(arr, len(surfaces), C.byref(cam), None, 0, C.byref(count)))
+    out = np.zeros((max(count.value, 1), 3), np.int32)
+    _check(lib().dpso_viewpoints(arr, len(surfaces), C.byref(cam), out.ctypes.data, count.value,
+                                 C.byref(count)))
+    return out[: count.value]
 
 
 def export_state(state: torch.Tensor, n: int, swarm_size: int, stream=None) -> dict:

@@ -209,6 +209,17 @@ def test_node_swap_on_a_random_matrix(dp):
     lockstep(dp, D, prm, [1, 3, 6], "swap_ties")
 
 
+@pytest.mark.parametrize("kw", [dict(ee_neighbourhood=NB, ee_trigger=2),
+                                dict(velocity_cap=4096, mutation_swaps=9, ee_trigger=2)],
+                         ids=["node_swap", "raw_velocity"])
+def test_largest_size_variants(dp, kw):
+    """The variants' kernels at n = 4096, where their LDS use is largest."""
+    n = 4096
+    D = scenes.random_dist(n, seed=n)
+    prm = scenes.swarm_params(4, 3, seed=5, instance=n, det_permille=250, **kw)
+    lockstep(dp, D, prm, [1, 3], f"n{n} {kw}")
+
+
 def test_raw_velocity_import_and_mode_check(dp):
     """Arbitrary transposition lists imported into a raw-velocity state move
     the swarm exactly as in the oracle; a state is refused by a run in the
