@@ -85,6 +85,8 @@ def lib():
             "or_round_len": (i64, [i64, i64, i64]),
             "or_segment_hits_box": (i32, [P, P, P, P]),
             "or_build_dist": (i32, [P, i32, P, i32, i32, P]),
+            "or_voxel_grid": (i32, [P, i32, P, i32, i32, i32, P, P, P]),
+            "or_build_dist_voxel": (i32, [P, i32, P, i32, i32, i32, i32, i32, i32, P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(_lib, name)
@@ -222,6 +224,34 @@ def build_dist(scene):
                              scene.clearance_mm, _p(D))
     if st != 0:
         raise ValueError(f"oracle build_dist failed with status {st}")
+    return D
+
+
+def voxel_grid(scene, voxel_mm):
+    """(dims (3,), origin (3,), occupancy uint8 [dims z][y][x]) of the planner's grid."""
+    vp = _i32(scene.vp_mm)
+    bx = _i32(scene.boxes_mm)
+    dims = np.zeros(3, np.int32)
+    origin = np.zeros(3, np.int64)
+    st = lib().or_voxel_grid(_p(vp), vp.shape[0], _p(bx) if bx.size else None, bx.shape[0],
+                             scene.clearance_mm, voxel_mm, _p(dims), _p(origin), None)
+    if st != 0:
+        raise ValueError(f"oracle voxel_grid failed with status {st}")
+    occ = np.zeros(int(np.prod(dims.astype(np.int64))), np.uint8)
+    lib().or_voxel_grid(_p(vp), vp.shape[0], _p(bx) if bx.size else None, bx.shape[0],
+                        scene.clearance_mm, voxel_mm, _p(dims), _p(origin), _p(occ))
+    return dims, origin, occ.reshape(dims[2], dims[1], dims[0])
+
+
+def build_dist_voxel(scene, voxel_mm, weights=(1, 1, 1)):
+    vp = _i32(scene.vp_mm)
+    bx = _i32(scene.boxes_mm)
+    n = vp.shape[0]
+    D = np.zeros((n, n), np.int32)
+    st = lib().or_build_dist_voxel(_p(vp), n, _p(bx) if bx.size else None, bx.shape[0],
+                                   scene.clearance_mm, voxel_mm, *[int(w) for w in weights], _p(D))
+    if st != 0:
+        raise ValueError(f"oracle build_dist_voxel failed with status {st}")
     return D
 
 

@@ -678,6 +678,173 @@ int32_t or_segment_hits_box(const int64_t A[3], const int64_t B[3], const int64_
     return frac_lt(lo_p, lo_q, hi_p, hi_q) && lo_p < lo_q && hi_p > 0;
 }
 
+/* ---------------------------------------------------------------------------
+ * Voxel-grid planner (Sect. 2.2): the workspace is divided into voxels of
+ * edge s; a voxel is occupied when its centre lies in the open interior of a
+ * box, and every voxel whose centre is within the UAV's size (the clearance)
+ * of an occupied centre is marked occupied too. A path moves between the 26
+ * neighbouring voxels; a step (alpha, beta, gamma) in {-1, 0, 1}^3 costs
+ * L = a1 alpha^2 + a2 beta^2 + a3 gamma^2 (eq. cost). It passes through free
+ * voxels only; its two end voxels (the viewpoints') may be occupied. The
+ * travelling cost of a pair is s times the least total step cost (the
+ * shortest path the A* search of the paper looks for); OR_D_INF when there is
+ * none.
+ *
+ * Grid: origin = (smallest coordinate of the viewpoints and box corners) - s
+ * per axis, dims = (largest - origin) / s + 2, voxel i covers
+ * [origin + i s, origin + (i+1) s).
+ * ------------------------------------------------------------------------- */
+int32_t or_voxel_grid(const int32_t *vp, int32_t n, const int32_t *boxes, int32_t nb, int32_t clearance,
+                      int32_t s, int32_t *dims, int64_t *origin, uint8_t *occ)
+{
+    if (n < 1 || nb < 0 || clearance < 0 || s < 1 || !vp || (nb > 0 && !boxes)) return OR_EINVAL;
+    int64_t lo[3], hi[3];
+    for (int a = 0; a < 3; a++) lo[a] = hi[a] = vp[a];
+    for (int32_t i = 0; i < n; i++)
+        for (int a = 0; a < 3; a++) {
+            if (vp[3 * i + a] < lo[a]) lo[a] = vp[3 * i + a];
+            if (vp[3 * i + a] > hi[a]) hi[a] = vp[3 * i + a];
+        }
+    for (int32_t b = 0; b < nb; b++)
+        for (int a = 0; a < 3; a++) {
+            if (boxes[6 * b + a] > boxes[6 * b + 3 + a]) return OR_EINVAL;
+            if (boxes[6 * b + a] < lo[a]) lo[a] = boxes[6 * b + a];
+            if (boxes[6 * b + 3 + a] > hi[a]) hi[a] = boxes[6 * b + 3 + a];
+        }
+    int64_t G = 1;
+    for (int a = 0; a < 3; a++) {
+        origin[a] = lo[a] - s;
+        int64_t d = (hi[a] - origin[a]) / s + 2;
+        if (d > (1 << 20)) return OR_ERANGE;
+        dims[a] = (int32_t)d;
+        G *= d;
+    }
+    if (G > ((int64_t)1 << 26)) return OR_ERANGE;
+    if (!occ) return OR_OK;
+    uint8_t *core = calloc((size_t)G, 1);
+    if (!core) return OR_ENOMEM;
+    for (int64_t v = 0; v < G; v++) {
+        int64_t idx[3] = {v % dims[0], (v / dims[0]) % dims[1], v / ((int64_t)dims[0] * dims[1])};
+        for (int32_t b = 0; b < nb && !core[v]; b++) {
+            int inside = 1;
+            for (int a = 0; a < 3; a++) {
+                int64_t c2 = 2 * origin[a] + (2 * idx[a] + 1) * s;   /* twice the centre */
+                if (!(2 * (int64_t)boxes[6 * b + a] < c2 && c2 < 2 * (int64_t)boxes[6 * b + 3 + a])) inside = 0;
+            }
+            core[v] = (uint8_t)inside;
+        }
+    }
+    int64_t R = clearance / s, r2 = (int64_t)clearance * clearance;
+    for (int64_t v = 0; v < G; v++) {
+        int64_t idx[3] = {v % dims[0], (v / dims[0]) % dims[1], v / ((int64_t)dims[0] * dims[1])};
+        uint8_t o = 0;
+        for (int64_t dk = -R; dk <= R && !o; dk++)
+            for (int64_t dj = -R; dj <= R && !o; dj++)
+                for (int64_t di = -R; di <= R && !o; di++) {
+                    if ((di * di + dj * dj + dk * dk) * s * s > r2) continue;
+                    int64_t i = idx[0] + di, j = idx[1] + dj, k = idx[2] + dk;
+                    if (i < 0 || j < 0 || k < 0 || i >= dims[0] || j >= dims[1] || k >= dims[2]) continue;
+                    o = core[i + dims[0] * (j + (int64_t)dims[1] * k)];
+                }
+        occ[v] = o;
+    }
+    free(core);
+    return OR_OK;
+}
+
+typedef struct { int64_t d; int64_t v; } heap_item;
+
+static void heap_push(heap_item *h, int64_t *len, heap_item it)
+{
+    int64_t i = (*len)++;
+    h[i] = it;
+    while (i > 0) {
+        int64_t p = (i - 1) / 2;
+        if (h[p].d <= h[i].d) break;
+        heap_item t = h[p]; h[p] = h[i]; h[i] = t;
+        i = p;
+    }
+}
+
+static heap_item heap_pop(heap_item *h, int64_t *len)
+{
+    heap_item top = h[0];
+    h[0] = h[--(*len)];
+    int64_t i = 0;
+    for (;;) {
+        int64_t l = 2 * i + 1, r = l + 1, m = i;
+        if (l < *len && h[l].d < h[m].d) m = l;
+        if (r < *len && h[r].d < h[m].d) m = r;
+        if (m == i) break;
+        heap_item t = h[m]; h[m] = h[i]; h[i] = t;
+        i = m;
+    }
+    return top;
+}
+
+int32_t or_build_dist_voxel(const int32_t *vp, int32_t n, const int32_t *boxes, int32_t nb, int32_t clearance,
+                            int32_t s, int32_t a1, int32_t a2, int32_t a3, int32_t *D)
+{
+    if (!D || a1 < 1 || a2 < 1 || a3 < 1 || a1 > (1 << 20) || a2 > (1 << 20) || a3 > (1 << 20)) return OR_EINVAL;
+    int32_t dims[3];
+    int64_t origin[3];
+    int32_t st = or_voxel_grid(vp, n, boxes, nb, clearance, s, dims, origin, NULL);
+    if (st) return st;
+    const int64_t G = (int64_t)dims[0] * dims[1] * dims[2];
+    uint8_t *occ = malloc((size_t)G);
+    int64_t *vox = malloc(sizeof(int64_t) * (size_t)n);
+    if (!occ || !vox) { free(occ); free(vox); return OR_ENOMEM; }
+    or_voxel_grid(vp, n, boxes, nb, clearance, s, dims, origin, occ);
+    for (int32_t i = 0; i < n; i++) {
+        int64_t id[3];
+        for (int a = 0; a < 3; a++) id[a] = ((int64_t)vp[3 * i + a] - origin[a]) / s;
+        vox[i] = id[0] + dims[0] * (id[1] + (int64_t)dims[1] * id[2]);
+    }
+    const int32_t wgt[3] = {a1, a2, a3};
+    int32_t status = OR_OK;
+    #pragma omp parallel for schedule(dynamic)
+    for (int32_t src = 0; src < n; src++) {
+        int64_t *dist = malloc(sizeof(int64_t) * (size_t)G);
+        heap_item *heap = malloc(sizeof(heap_item) * (size_t)(27 * G + 1));
+        int64_t hl = 0;
+        for (int64_t v = 0; v < G; v++) dist[v] = INT64_MAX;
+        dist[vox[src]] = 0;
+        heap_push(heap, &hl, (heap_item){0, vox[src]});
+        while (hl > 0) {
+            heap_item it = heap_pop(heap, &hl);
+            int64_t u = it.v;
+            if (it.d != dist[u]) continue;            /* stale entry */
+            if (occ[u] && u != vox[src]) continue;    /* an occupied end voxel: not passed through */
+            int64_t ui = u % dims[0], uj = (u / dims[0]) % dims[1], uk = u / ((int64_t)dims[0] * dims[1]);
+            for (int dk = -1; dk <= 1; dk++)
+                for (int dj = -1; dj <= 1; dj++)
+                    for (int di = -1; di <= 1; di++) {
+                        if (!di && !dj && !dk) continue;
+                        int64_t i = ui + di, j = uj + dj, k = uk + dk;
+                        if (i < 0 || j < 0 || k < 0 || i >= dims[0] || j >= dims[1] || k >= dims[2]) continue;
+                        int64_t v = i + dims[0] * (j + (int64_t)dims[1] * k);
+                        int64_t nd = it.d + (int64_t)wgt[0] * di * di + (int64_t)wgt[1] * dj * dj +
+                                     (int64_t)wgt[2] * dk * dk;
+                        if (nd < dist[v]) { dist[v] = nd; heap_push(heap, &hl, (heap_item){nd, v}); }
+                    }
+        }
+        for (int32_t j = 0; j < n; j++) {
+            int64_t d = dist[vox[j]];
+            if (d == INT64_MAX) { D[(int64_t)src * n + j] = OR_D_INF; continue; }
+            d *= s;
+            if (d >= OR_D_INF) {
+                #pragma omp critical
+                status = OR_ERANGE;
+                d = OR_D_INF;
+            }
+            D[(int64_t)src * n + j] = (int32_t)d;
+        }
+        free(dist); free(heap);
+    }
+    free(occ); free(vox);
+    return status;
+}
+
 int32_t or_build_dist(const int32_t *vp, int32_t n, const int32_t *boxes, int32_t nb,
                       int32_t clearance, int32_t *D)
 {
