@@ -294,6 +294,65 @@ def bench_ablation(trials: int, generations: int):
     return out
 
 
+VOXEL_CASES = [("facade n=30", 1, 250), ("bridge girder n=200", 2, 250),
+               ("facade n=1000", 3, 500), ("facade n=1000", 3, 250), ("facade n=1000", 3, 125)]
+
+
+def bench_voxel(reps: int, oracle_seconds: float):
+    """The voxel-grid planner (unit step weights) on the three synthetic
+    scenes at several voxel edges: milliseconds per all-pairs build on the GPU
+    (the whole call: host set-up, uploads, kernels, synchronisation), the
+    visibility-graph builder on the same scene for comparison, and the oracle
+    on the host cores while a case stays under `oracle_seconds`."""
+    import ctypes as C
+    import numpy as np
+    import torch
+    import oracle
+    from paper_1706_04399_amd import dpso, scenes
+
+    gomp = C.CDLL("libgomp.so.1")
+    out = {"metric": "voxel_planner_ms", "unit": "ms", "higher_is_better": False, "n_gpus": 1,
+           "dtype": "int32", "data": "synthetic", "weights": [1, 1, 1], "reps": reps,
+           "oracle_threads": int(gomp.omp_get_max_threads()), "cases": []}
+    dpso.build_dist_voxel(scenes.workload(1)[0], 500)      # untimed: loads the kernels
+    rate = None
+    for label, k, s in VOXEL_CASES:
+        sc = scenes.workload(k)[0]
+        row = {"scene": label, "voxel_mm": s, "n": sc.n}
+        vp = sc.vp_mm.astype(np.int64)
+        pts = [vp] + ([sc.boxes_mm[:, :3], sc.boxes_mm[:, 3:]] if len(sc.boxes_mm) else [])
+        lo = np.concatenate(pts).min(axis=0) - s
+        hi = np.concatenate(pts).max(axis=0)
+        dims = (hi - lo) // s + 2
+        row["grid"] = [int(d) for d in dims]
+        row["voxels"] = int(np.prod(dims))
+        D = dpso.build_dist_voxel(sc, s)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            D = dpso.build_dist_voxel(sc, s)
+        torch.cuda.synchronize()
+        row["gpu_ms"] = round((time.perf_counter() - t0) / reps * 1e3, 3)
+        row["unreachable_pairs"] = int((D == dpso.D_INF).sum().item())
+        dpso.build_dist(sc)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            dpso.build_dist(sc)
+        torch.cuda.synchronize()
+        row["visibility_builder_ms"] = round((time.perf_counter() - t0) / reps * 1e3, 3)
+        size = row["voxels"] * sc.n
+        if rate is None or size / rate < oracle_seconds:
+            t0 = time.perf_counter()
+            ref = oracle.build_dist_voxel(sc, s)
+            dt = time.perf_counter() - t0
+            row["oracle_ms"] = round(dt * 1e3, 1)
+            row["equal_to_oracle"] = bool(np.array_equal(ref, D.cpu().numpy()))
+            rate = size / dt                  # voxel-sources per second, to skip slow cases
+        out["cases"].append(row)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -315,6 +374,8 @@ def main():
     ap.add_argument("--ablation", type=int, default=0,
                     help="run the augmentation ablation with this many trials per variant instead")
     ap.add_argument("--ablation-generations", type=int, default=200)
+    ap.add_argument("--voxel", type=int, default=0,
+                    help="time the voxel-grid planner (this many builds per case) instead")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (each swarm runs "
@@ -326,6 +387,9 @@ def main():
         return
     if args.ablation:
         print(json.dumps(bench_ablation(args.ablation, args.ablation_generations)), flush=True)
+        return
+    if args.voxel:
+        print(json.dumps(bench_voxel(args.voxel, args.cpu_seconds)), flush=True)
         return
     if args.serve:
         print(json.dumps(bench_serve(args.serve, args.rate, min(args.serve_warmup, args.serve // 4),

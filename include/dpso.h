@@ -185,6 +185,35 @@ typedef struct {
 dpso_status dpso_viewpoints(const dpso_surface *surfaces, int32_t count, const dpso_camera *camera,
                             int32_t *vp_mm, int32_t max_n, int32_t *n_out);
 
+/* Voxel-grid planner (Sect. 2.2, eq. cost), an alternative source of the
+ * travelling costs. Voxels of edge voxel_mm cover the scene with a one-voxel
+ * margin (origin = smallest viewpoint or box coordinate - voxel_mm per axis,
+ * (largest - origin) / voxel_mm + 2 voxels per axis); a voxel is occupied when
+ * its centre is in the open interior of a box, and so is every voxel whose
+ * centre is within clearance_mm (the UAV's size) of an occupied centre. A path
+ * steps between the 26 neighbouring voxels; step (a, b, c) in {-1,0,1}^3 costs
+ * weight[0] a^2 + weight[1] b^2 + weight[2] c^2. It passes through free voxels
+ * only; its end voxels (those holding the two viewpoints) may be occupied.
+ * D[i][j] = voxel_mm * least total step cost, DPSO_D_INF if no path. */
+typedef struct {
+    int32_t voxel_mm;   /* voxel edge, >= 1               */
+    int32_t weight[3];  /* a1, a2, a3 of eq. cost, 1..2^20 */
+} dpso_voxel_params;
+
+/* Device workspace for dpso_build_dist_voxel; 0 for invalid arguments or a
+ * grid above 2^26 voxels (or 2^20 along an axis). It holds the occupancy
+ * grids and the search arrays of min(n, 1024) sources searched at once, at
+ * most 16 GiB of those (a larger problem runs its sources in several
+ * chunks). */
+size_t dpso_voxel_work_bytes(const dpso_scene *scene, const dpso_voxel_params *params);
+
+/* Travelling costs by the voxel-grid planner: writes d_dist (device int32
+ * [n][n]); d_work (device, dpso_voxel_work_bytes) is scratch. Synchronises
+ * `stream`. DPSO_E_RANGE if a finite path cost reaches DPSO_D_INF (those
+ * entries are DPSO_D_INF) or the grid is too large. */
+dpso_status dpso_build_dist_voxel(const dpso_scene *scene, const dpso_voxel_params *params,
+                                  int32_t *d_dist, void *d_work, size_t work_bytes, void *stream);
+
 /* Bytes of device workspace dpso_build_dist needs for this scene size. */
 size_t dpso_dist_work_bytes(int32_t n, int32_t n_boxes);
 

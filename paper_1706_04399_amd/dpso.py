@@ -44,6 +44,10 @@ class Camera(C.Structure):
                 ("overlap_permille", C.c_int32), ("focal_um", C.c_int32), ("sensor_um", C.c_int32)]
 
 
+class VoxelParams(C.Structure):
+    _fields_ = [("voxel_mm", C.c_int32), ("weight", C.c_int32 * 3)]
+
+
 class Params(C.Structure):
     _fields_ = [("swarm_size", C.c_int32), ("max_generations", C.c_int32),
                 ("w_q16", C.c_uint32), ("phi1_q16", C.c_uint32), ("phi2_q16", C.c_uint32),
@@ -104,6 +108,9 @@ EXPORTS = {
                                       C.c_void_p]),
     "dpso_viewpoints": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32,
                                     C.c_void_p]),
+    "dpso_voxel_work_bytes": (C.c_size_t, [C.c_void_p, C.c_void_p]),
+    "dpso_build_dist_voxel": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,
+                                          C.c_void_p]),
 }
 
 _lib = None
@@ -233,6 +240,34 @@ def get_best(state: torch.Tensor, stream=None):
     _check(lib().dpso_get_best(_dev(state, torch.uint8), tour.ctypes.data, C.byref(cost),
                                C.byref(gen), trace.ctypes.data, _stream(stream)))
     return tour, cost.value, gen.value, trace[: gen.value + 1]
+
+
+def _voxel_args(scene, voxel_mm, weights):
+    vp = np.ascontiguousarray(scene.vp_mm, dtype=np.int32)
+    bx = np.ascontiguousarray(scene.boxes_mm, dtype=np.int32)
+    sc = Scene(vp.ctypes.data, vp.shape[0], bx.ctypes.data if bx.size else None, bx.shape[0],
+               int(scene.clearance_mm))
+    vpp = VoxelParams(int(voxel_mm), (C.c_int32 * 3)(*[int(w) for w in weights]))
+    return vp, bx, sc, vpp
+
+
+def voxel_work_bytes(scene, voxel_mm: int, weights=(1, 1, 1)) -> int:
+    vp, bx, sc, vpp = _voxel_args(scene, voxel_mm, weights)
+    return int(lib().dpso_voxel_work_bytes(C.byref(sc), C.byref(vpp)))
+
+
+def build_dist_voxel(scene, voxel_mm: int, weights=(1, 1, 1), device="cuda", stream=None) -> torch.Tensor:
+    """Travelling costs from the voxel-grid planner (device int32 [n][n])."""
+    vp, bx, sc, vpp = _voxel_args(scene, voxel_mm, weights)
+    wb = int(lib().dpso_voxel_work_bytes(C.byref(sc), C.byref(vpp)))
+    if wb == 0:
+        _check(lib().dpso_build_dist_voxel(C.byref(sc), C.byref(vpp), None, None, 0, _stream(stream)))
+    n = vp.shape[0]
+    D = torch.empty((n, n), dtype=torch.int32, device=device)
+    work = torch.empty(wb, dtype=torch.uint8, device=device)
+    _check(lib().dpso_build_dist_voxel(C.byref(sc), C.byref(vpp), _dev(D, torch.int32),
+                                       _dev(work, torch.uint8), wb, _stream(stream)))
+    return D
 
 
 def viewpoints(surfaces, camera: dict) -> np.ndarray:

@@ -105,6 +105,37 @@ def test_build_dist_validation(dp):
     assert L.dpso_build_dist(C.byref(sc), fake, fake, 16, None) == dp.E_NOMEM
 
 
+def test_voxel_planner_validation(dp):
+    """Host checks of the voxel planner: bad arguments give a zero workspace
+    size and an error before any device work."""
+    import numpy as np
+    L = dp.lib()
+    fake = C.c_void_p(0x1000)
+    vp = np.array([[0, 0, 0], [5000, 0, 0]], np.int32)
+    box = np.array([[1000, -500, -500, 2000, 500, 500]], np.int32)
+    sc = dp.Scene(vp.ctypes.data, 2, box.ctypes.data, 1, 300)
+    good = dp.VoxelParams(250, (C.c_int32 * 3)(1, 2, 3))
+    need = L.dpso_voxel_work_bytes(C.byref(sc), C.byref(good))
+    assert need > 0
+    assert L.dpso_build_dist_voxel(C.byref(sc), C.byref(good), fake, fake, need - 1, None) == dp.E_NOMEM
+    assert L.dpso_build_dist_voxel(C.byref(sc), C.byref(good), None, fake, need, None) == dp.E_INVAL
+    for s, w in [(0, (1, 1, 1)), (-3, (1, 1, 1)), (100, (0, 1, 1)), (100, (1, 1, -2)),
+                 (100, (1, 1 << 21, 1))]:
+        bad = dp.VoxelParams(s, (C.c_int32 * 3)(*w))
+        assert L.dpso_voxel_work_bytes(C.byref(sc), C.byref(bad)) == 0
+        assert L.dpso_build_dist_voxel(C.byref(sc), C.byref(bad), fake, fake, 1 << 30, None) == dp.E_INVAL
+    # 1 mm voxels: 5003 x 1003 x 1003 here, 10003^3 over a 10 m cube: above 2^26
+    assert L.dpso_voxel_work_bytes(C.byref(sc), C.byref(dp.VoxelParams(1, (C.c_int32 * 3)(1, 1, 1)))) == 0
+    cube = np.array([[0, 0, 0], [10000, 10000, 10000]], np.int32)
+    sc2 = dp.Scene(cube.ctypes.data, 2, None, 0, 0)
+    one = dp.VoxelParams(1, (C.c_int32 * 3)(1, 1, 1))
+    assert L.dpso_voxel_work_bytes(C.byref(sc2), C.byref(one)) == 0
+    assert L.dpso_build_dist_voxel(C.byref(sc2), C.byref(one), fake, fake, 1 << 30, None) == dp.E_RANGE
+    assert L.dpso_voxel_work_bytes(None, C.byref(good)) == 0
+    neg = dp.Scene(vp.ctypes.data, 2, box.ctypes.data, 1, -1)
+    assert L.dpso_voxel_work_bytes(C.byref(neg), C.byref(good)) == 0
+
+
 def test_library_does_not_link_the_oracle(dp):
     data = open(dp._LIB_PATH, "rb").read()
     assert b"liboracle" not in data and b"or_build_dist" not in data
