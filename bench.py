@@ -20,6 +20,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+VALU_LANE_OPS_PER_S = 256 * 4 * 16 * 2.4e9
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_facade1000.md")
 KERNEL_SRC = os.path.join(ROOT, "paper_1706_04399_amd", "csrc", "twoopt.hip")
 
@@ -444,6 +445,16 @@ def main():
         "phases_ms": {k: round(v, 2) for k, v in phases.items() if k.startswith("ms_")},
         "best_cost_mm": info1["best_cost"],
     }
+    # the distance builder, timed on its own after the timed region: median of 5
+    build_ms = []
+    for _ in range(6):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        dpso.build_dist(sc, out=D)
+        b.record()
+        b.synchronize()
+        build_ms.append(a.elapsed_time(b))
+    line["build_dist_ms_median5"] = round(sorted(build_ms[1:])[2], 3)
     if not args.no_ceilings:
         c = measure_ceilings()
         bpi = 4 * n * (n - 1)                       # algorithmic bytes per particle-iteration
@@ -458,6 +469,8 @@ def main():
             "exchange_lds_bound_us": round(lds_s * 1e6, 1),
             "exchange_measured_us": round(avg_launch_s * 1e6, 1),
             "exchange_frac_of_lds_bound": round(lds_s / avg_launch_s, 4),
+            # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, at ~8 integer operations per exchange
+            "valu_bound_piters_per_s": round(VALU_LANE_OPS_PER_S / (8 * n * (n - 3) / 2), 1),
         })
         line["ceilings"] = c
     if not args.no_cpu:

@@ -214,6 +214,18 @@ size_t dpso_voxel_work_bytes(const dpso_scene *scene, const dpso_voxel_params *p
 dpso_status dpso_build_dist_voxel(const dpso_scene *scene, const dpso_voxel_params *params,
                                   int32_t *d_dist, void *d_work, size_t work_bytes, void *stream);
 
+/* Checks a device matrix against the contract every swarm call relies on
+ * (Sect. 2: one symmetric travelling cost per pair of viewpoints, none from a
+ * viewpoint to itself; Sect. 2.3: a blocked pair costs DPSO_D_INF):
+ * D[i][i] = 0, D[i][j] = D[j][i] and 0 <= D[i][j] <= DPSO_D_INF. d_dist:
+ * device int32 [n][n]; d_work: device scratch of at least 8 bytes. *h_bad
+ * receives the row-major index i * n + j of the first entry that breaks the
+ * contract, or -1. Synchronises `stream`. DPSO_OK if the matrix holds,
+ * DPSO_E_RANGE if not. The swarm calls do not run this check themselves (it
+ * is a full pass over the matrix); both builders produce matrices that hold. */
+dpso_status dpso_check_dist(const int32_t *d_dist, int32_t n, void *d_work, size_t work_bytes,
+                            int64_t *h_bad, void *stream);
+
 /* Bytes of device workspace dpso_build_dist needs for this scene size. */
 size_t dpso_dist_work_bytes(int32_t n, int32_t n_boxes);
 

@@ -62,6 +62,7 @@ def lib():
             "or_philox4x64_10": (None, [P, P, P]),
             "or_draws": (None, [u64, u64, u64, u64, u64, i32, P]),
             "or_tour_cost": (i64, [P, i32, P]),
+            "or_check_dist": (i64, [P, i32]),
             "or_apply_swaps": (None, [P, i32, P, i32]),
             "or_bss": (i32, [P, P, i32, P]),
             "or_truncate_counts": (None, [i32, i32, i32, u32, u32, u32, u32, u32, P]),
@@ -213,6 +214,12 @@ def round_len(dx, dy, dz) -> int:
 def segment_hits_box(A, B, L, H) -> bool:
     a = [np.ascontiguousarray(v, dtype=np.int64) for v in (A, B, L, H)]
     return bool(lib().or_segment_hits_box(*[_p(v) for v in a]))
+
+
+def check_dist(D):
+    """Row-major index of the first entry of D breaking the matrix contract, or -1."""
+    D = _i32(D)
+    return int(lib().or_check_dist(_p(D), D.shape[0]))
 
 
 def build_dist(scene):

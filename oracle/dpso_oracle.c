@@ -143,6 +143,23 @@ int64_t or_tour_cost(const int32_t *D, int32_t n, const int32_t *x)
     return c;
 }
 
+/* The matrix contract the swarm relies on (Sect. 2: a symmetric travelling
+ * cost between every pair of viewpoints, none from a viewpoint to itself; a
+ * blocked pair costs the very large OR_D_INF, Sect. 2.3): D[i][i] = 0,
+ * D[i][j] = D[j][i] and 0 <= D[i][j] <= OR_D_INF. Returns the row-major index
+ * i * n + j of the first entry that breaks it, or -1. */
+int64_t or_check_dist(const int32_t *D, int32_t n)
+{
+    for (int64_t i = 0; i < n; i++)
+        for (int64_t j = 0; j < n; j++) {
+            int32_t v = D[i * n + j];
+            if (v < 0 || v > OR_D_INF) return i * n + j;
+            if (i == j && v != 0) return i * n + j;
+            if (v != D[j * n + i]) return i * n + j;
+        }
+    return -1;
+}
+
 /* ---------------------------------------------------------------------------
  * Velocity operators (Sect. 3.1).
  * A transposition (a, b) exchanges the places of the LABELS a and b in the

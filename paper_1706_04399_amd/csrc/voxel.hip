@@ -371,11 +371,15 @@ Bricks bricks_of(const Grid &g)
 // Per-source arrays: costs (64 words a brick), tags and two brick lists.
 size_t per_source_bytes(int64_t NB) { return size_t(NB) * (64 * 4 + 3 * 4); }
 
-// Sources per chunk: 16 GiB of per-source arrays at most.
+// Sources per chunk: 16 GiB of per-source arrays at most, at most 1024, and
+// the chunks evened out (a short last chunk would cost a whole search
+// latency for a few sources).
 int32_t chunk_sources(int32_t n, int64_t NB)
 {
     const int64_t k = std::max<int64_t>(1, (int64_t(16) << 30) / int64_t(per_source_bytes(NB)));
-    return int32_t(std::min<int64_t>({k, n, 1024}));
+    const int64_t most = std::min<int64_t>({k, n, 1024});
+    const int64_t chunks = (n + most - 1) / most;
+    return int32_t((n + chunks - 1) / chunks);
 }
 
 // The distance transform's arrays (24 bytes per voxel) and the per-source

@@ -108,6 +108,7 @@ EXPORTS = {
                                       C.c_void_p]),
     "dpso_viewpoints": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32,
                                     C.c_void_p]),
+    "dpso_check_dist": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p]),
     "dpso_voxel_work_bytes": (C.c_size_t, [C.c_void_p, C.c_void_p]),
     "dpso_build_dist_voxel": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,
                                           C.c_void_p]),
@@ -188,6 +189,20 @@ def build_dist(scene, out: torch.Tensor | None = None, stream=None, device=None)
     _check(lib().dpso_build_dist(C.byref(sc), _dev(out, torch.int32), C.c_void_p(work.data_ptr()),
                                  work.numel(), _stream(stream)))
     return out
+
+
+def check_dist(D: torch.Tensor, stream=None) -> int:
+    """Row-major index of the first entry of a device matrix that breaks the
+    matrix contract (zero diagonal, symmetric, 0..D_INF), or -1."""
+    if D.dim() != 2 or D.shape[0] != D.shape[1]:
+        raise ValueError("expected a square matrix")
+    work = torch.empty(8, dtype=torch.uint8, device=D.device)
+    bad = C.c_int64(-1)
+    st = lib().dpso_check_dist(_dev(D, torch.int32), D.shape[0], C.c_void_p(work.data_ptr()), 8,
+                               C.byref(bad), _stream(stream))
+    if st not in (OK, E_RANGE):
+        _check(st)
+    return int(bad.value)
 
 
 def new_state(n: int, params, device="cuda") -> torch.Tensor:

@@ -69,6 +69,42 @@ def test_build_dist_unreachable_pair(dp):
     assert got[0, 1] == dp.D_INF
 
 
+@pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 200, 1000, 4096])
+def test_check_dist_matches_oracle(dp, n):
+    """The device check reports the oracle's first broken entry, across tile
+    edges and with breaks planted in several places."""
+    note(f"check_dist n={n}")
+    rng = np.random.default_rng(n)
+    D = scenes.random_dist(n, seed=n)
+    assert dp.check_dist(_dev(D)) == oracle.check_dist(D) == -1
+    if n == 1:
+        D1 = np.array([[3]], np.int32)
+        assert dp.check_dist(_dev(D1)) == oracle.check_dist(D1) == 0
+        return
+    for trial in range(6):
+        E = D.copy()
+        for _ in range(int(rng.integers(1, 4))):
+            i, j = (int(v) for v in rng.integers(0, n, size=2))
+            kind = trial % 4
+            if kind == 0:
+                E[i, j] = -1 - int(rng.integers(0, 9))
+            elif kind == 1:
+                E[i, j] = (1 << 28) + int(rng.integers(0, 9))
+            elif kind == 2:
+                E[i, i] = 1 + int(rng.integers(0, 9))
+            else:
+                E[i, j] += 1 if i != j else 0
+        assert dp.check_dist(_dev(E)) == oracle.check_dist(E), (n, trial)
+
+
+def test_check_dist_on_built_matrices(dp):
+    note("check_dist built matrices")
+    for k in (1, 2, 3):
+        D = dp.build_dist(scenes.workload(k)[0])
+        assert dp.check_dist(D) == -1
+    assert dp.check_dist(dp.build_dist_voxel(scenes.workload(2)[0], 500)) == -1
+
+
 def lockstep(dp, D, prm, checkpoints, label):
     """Runs library and oracle from the same initial swarm, comparing the whole
     state at each checkpoint generation."""

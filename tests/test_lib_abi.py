@@ -136,6 +136,19 @@ def test_voxel_planner_validation(dp):
     assert L.dpso_voxel_work_bytes(C.byref(neg), C.byref(good)) == 0
 
 
+def test_check_dist_validation(dp):
+    L = dp.lib()
+    fake = C.c_void_p(0x1000)
+    bad = C.c_int64(7)
+    assert L.dpso_check_dist(None, 10, fake, 8, C.byref(bad), None) == dp.E_INVAL
+    assert L.dpso_check_dist(fake, 10, None, 8, C.byref(bad), None) == dp.E_INVAL
+    assert L.dpso_check_dist(fake, 10, fake, 8, None, None) == dp.E_INVAL
+    assert L.dpso_check_dist(fake, 0, fake, 8, C.byref(bad), None) == dp.E_RANGE
+    assert L.dpso_check_dist(fake, 4097, fake, 8, C.byref(bad), None) == dp.E_RANGE
+    assert L.dpso_check_dist(fake, 10, fake, 7, C.byref(bad), None) == dp.E_NOMEM
+    assert bad.value == 7                                   # untouched on a host-side error
+
+
 def test_library_does_not_link_the_oracle(dp):
     data = open(dp._LIB_PATH, "rb").read()
     assert b"liboracle" not in data and b"or_build_dist" not in data

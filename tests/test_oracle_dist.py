@@ -105,3 +105,50 @@ def test_unreachable_pair_gets_large_cost(orc):
     sc = scenes.Scene(np.array([(0, 0, 0), (10000, 0, 0)]), np.array(slabs), 0)
     D = orc.build_dist(sc)
     assert D[0, 1] == D[1, 0] == (1 << 28) - 1
+
+
+# ------------------------------------------------------ the matrix contract
+
+D_INF = (1 << 28) - 1
+
+
+def plant(n, seed, kind, i, j):
+    """A valid symmetric matrix with one planted break at (i, j)."""
+    D = scenes.random_dist(n, seed=seed, max_mm=D_INF).astype(np.int64)
+    if kind == "negative":
+        D[i, j] = D[j, i] = -1
+    elif kind == "above_inf":
+        D[i, j] = D[j, i] = D_INF + 1
+    elif kind == "diagonal":
+        D[i, i] = 5
+        j = i
+    elif kind == "asymmetric":
+        D[i, j] += 1
+    return D.astype(np.int32), min(i, j) * n + max(i, j)
+
+
+def test_check_dist_accepts_valid_matrices(orc):
+    for sc in (scenes.workload(1)[0], scenes.random_points(40, seed=2, n_boxes=3)):
+        assert orc.check_dist(orc.build_dist(sc)) == -1
+    D = scenes.random_dist(17, seed=1)
+    D[2, 9] = D[9, 2] = D_INF                     # a blocked pair is allowed
+    assert orc.check_dist(D) == -1
+    assert orc.check_dist(np.zeros((1, 1), np.int32)) == -1
+
+
+@pytest.mark.parametrize("kind", ["negative", "above_inf", "diagonal", "asymmetric"])
+def test_check_dist_finds_a_planted_break(orc, kind):
+    rng = np.random.default_rng(len(kind))
+    for n in (2, 7, 30):
+        for _ in range(5):
+            i, j = (int(v) for v in rng.choice(n, size=2, replace=False))
+            D, first = plant(n, seed=n, kind=kind, i=i, j=j)
+            assert orc.check_dist(D) == first, (kind, n, i, j)
+
+
+def test_check_dist_reports_the_first_of_several(orc):
+    D = scenes.random_dist(12, seed=4)
+    D[7, 3] += 1                                   # asymmetric: first seen at row 3
+    D[5, 5] = 1
+    D[9, 1] = D[1, 9] = -4
+    assert orc.check_dist(D) == 1 * 12 + 9         # row-major order: (1, 9) < (3, 7) < (5, 5)
