@@ -65,6 +65,7 @@ def measure_ceilings():
     lib.ceil_l2_gather.argtypes = [C.c_void_p, C.c_uint32, i32, i32, C.c_void_p, C.c_void_p]
     lib.ceil_lds_gather.argtypes = [i32, i32, C.c_void_p, C.c_void_p]
     lib.ceil_lds_write.argtypes = [i32, i32, C.c_void_p, C.c_void_p]
+    lib.ceil_lds_dma.argtypes = [C.c_void_p, i32, i32, i32, i32, C.c_void_p, C.c_void_p]
     stream = torch.cuda.current_stream()
     sh = C.c_void_p(stream.cuda_stream)
     big = torch.randint(0, 1 << 20, (4 << 20,), dtype=torch.int32, device="cuda")   # 16 MB
@@ -98,9 +99,14 @@ def measure_ceilings():
     lds_gather = blocks * 256 * reps * 16 / t / 1e9               # G reads/s
     t = timed(lambda: lib.ceil_lds_write(blocks, reps, C.c_void_p(sink.data_ptr()), sh))
     lds_write = blocks * 4 * reps * 4096 / t / 1e9               # GB/s
+    reps, waves = 200, 4096
+    t = timed(lambda: lib.ceil_lds_dma(C.c_void_p(mat.data_ptr()), 1000, 1000, waves, reps,
+                                       C.c_void_p(sink.data_ptr()), sh))
+    lds_dma = waves * (reps + 1) * 4096 / t / 1e9                 # GB/s of 4 KB rows staged
     torch.cuda.synchronize()
     return {"l2_stream_GBs": round(l2_stream, 1), "l2_random_gather_GBs": round(l2_gather, 1),
-            "lds_random_read_G_per_s": round(lds_gather, 1), "lds_row_write_GBs": round(lds_write, 1)}
+            "lds_random_read_G_per_s": round(lds_gather, 1), "lds_row_write_GBs": round(lds_write, 1),
+            "lds_dma_row_GBs": round(lds_dma, 1)}
 
 
 def cpu_baseline(seconds: float):
@@ -459,16 +465,28 @@ def main():
         c = measure_ceilings()
         bpi = 4 * n * (n - 1)                       # algorithmic bytes per particle-iteration
         per_launch = sweeps / launches              # sweeps in one exchange launch
-        # LDS time the exchange kernel cannot go below at the measured rates:
-        # one random read per exchange, one staged 4n-byte row per row
-        lds_s = per_launch * (n * (n - 3) / 2 / (c["lds_random_read_G_per_s"] * 1e9) +
-                              4 * n * (n - 2) / (c["lds_row_write_GBs"] * 1e9))
+        # time the exchange kernel cannot go below at the measured rates: one
+        # random LDS read per exchange, and one staged row per row of the sweep
+        # (n - 1 rows). Rows that go straight from memory into LDS (n a
+        # multiple of 4) stream while the gathers run: the bound is the larger
+        # of the two. Rows staged through registers take LDS store time too.
+        gather_s = per_launch * n * (n - 3) / 2 / (c["lds_random_read_G_per_s"] * 1e9)
+        mb = next(m for m in (1, 2, 4, 8, 16) if n <= 64 * m)
+        row_bytes = 1024 * ((mb + 3) // 4)          # staged per row (whole 1 KB chunks)
+        if n % 4 == 0:
+            stage_s = per_launch * (n - 1) * row_bytes / (c["lds_dma_row_GBs"] * 1e9)
+            bound_s = max(gather_s, stage_s)
+        else:
+            stage_s = per_launch * (n - 2) * 4 * n / (c["lds_row_write_GBs"] * 1e9)
+            bound_s = gather_s + stage_s
         c.update({
             "l2_stream_bound_piters_per_s": round(c["l2_stream_GBs"] * 1e9 / bpi, 1),
             "l2_gather_bound_piters_per_s": round(c["l2_random_gather_GBs"] * 1e9 / bpi, 1),
-            "exchange_lds_bound_us": round(lds_s * 1e6, 1),
+            "exchange_gather_us": round(gather_s * 1e6, 1),
+            "exchange_staging_us": round(stage_s * 1e6, 1),
+            "exchange_bound_us": round(bound_s * 1e6, 1),
             "exchange_measured_us": round(avg_launch_s * 1e6, 1),
-            "exchange_frac_of_lds_bound": round(lds_s / avg_launch_s, 4),
+            "exchange_frac_of_bound": round(bound_s / avg_launch_s, 4),
             # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, at ~8 integer operations per exchange
             "valu_bound_piters_per_s": round(VALU_LANE_OPS_PER_S / (8 * n * (n - 3) / 2), 1),
         })

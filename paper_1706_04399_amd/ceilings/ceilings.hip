@@ -9,7 +9,11 @@
 //   ceil_lds_gather  random 4-byte LDS reads within a 4 KB row per wave
 //                    (the edge-exchange gather)
 //   ceil_lds_write   16-byte LDS writes of whole 4 KB rows per wave (the
-//                    edge-exchange row staging)
+//                    edge-exchange row staging through registers)
+//   ceil_lds_dma     rows of an L2-resident matrix loaded straight into LDS
+//                    (global_load_lds_dwordx4), one wave per block and one
+//                    row in flight (the edge-exchange row staging for rows
+//                    that start on 16 bytes)
 //
 // Every kernel accumulates what it reads and stores only if the sum equals a
 // value it never reaches, so the reads cannot be dropped and nothing is
@@ -109,6 +113,33 @@ __global__ __launch_bounds__(kThreads) void k_lds_write(int reps, int *sink)
     if (u.x + u.y + u.z + u.w == kNever) sink[blockIdx.x * kThreads + threadIdx.x] = u.x;
 }
 
+// One wave per block, two 4 KB LDS buffers: row t + 1 is in flight while
+// row t, landed, is read once. Rows r = (7 b + 13 t) mod rows; chunk indices
+// are clamped to the row.
+__global__ __launch_bounds__(64) void k_lds_dma(const int *__restrict__ mat, int rows, int row_ints, int reps,
+                                               int *sink)
+{
+    typedef __attribute__((address_space(1))) const void GV;
+    typedef __attribute__((address_space(3))) void LV;
+    __shared__ __align__(16) int buf[2][kRow];
+    const int l = threadIdx.x, q = row_ints / 4 - 1;
+    int r = int((7ll * blockIdx.x) % rows), acc = 0;
+    for (int k = 0; k < kRow / 256; ++k)
+        __builtin_amdgcn_global_load_lds((GV *)(mat + size_t(r) * row_ints + 4 * min(l + 64 * k, q)),
+                                         (LV *)(buf[0] + 256 * k), 16, 0, 0);
+    for (int t = 0; t < reps; ++t) {
+        r = (r + 13) % rows;
+        for (int k = 0; k < kRow / 256; ++k)
+            __builtin_amdgcn_global_load_lds((GV *)(mat + size_t(r) * row_ints + 4 * min(l + 64 * k, q)),
+                                             (LV *)(buf[(t + 1) & 1] + 256 * k), 16, 0, 0);
+        __builtin_amdgcn_s_waitcnt(0x0F74);  // vmcnt(4): row t has landed
+        acc += buf[t & 1][(l * 37 + t) & (kRow - 1)];
+        __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0) before the buffer is refilled
+    }
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+    if (acc == kNever) sink[blockIdx.x * 64 + l] = acc;
+}
+
 }  // namespace
 
 extern "C" {
@@ -148,6 +179,18 @@ int ceil_lds_write(int blocks, int reps, int *sink, hipStream_t stream)
 {
     if (!sink || blocks <= 0 || reps <= 0) return int(hipErrorInvalidValue);
     k_lds_write<<<blocks, kThreads, 0, stream>>>(reps, sink);
+    return int(hipGetLastError());
+}
+
+// mat: device, rows x row_ints ints, row_ints a multiple of 4 in [4, 1024];
+// sink: >= blocks * 64 ints. Stages blocks * (reps + 1) rows of 4096 LDS
+// bytes each (lanes past the row repeat its last 16 bytes).
+int ceil_lds_dma(const void *mat, int rows, int row_ints, int blocks, int reps, int *sink, hipStream_t stream)
+{
+    if (!mat || !sink || rows <= 0 || blocks <= 0 || reps <= 0 || row_ints < 4 || row_ints > kRow ||
+        row_ints % 4 != 0)
+        return int(hipErrorInvalidValue);
+    k_lds_dma<<<blocks, 64, 0, stream>>>(static_cast<const int *>(mat), rows, row_ints, reps, sink);
     return int(hipGetLastError());
 }
 

@@ -137,6 +137,12 @@ __device__ __forceinline__ void twoopt_rows_body(const Inst &I, int p)
 #ifndef DPSO_2OPT_WAVES
 #define DPSO_2OPT_WAVES 4
 #endif
+// Rows that start on 16 bytes (n a multiple of 4) can go from memory straight
+// into LDS (global_load_lds_dwordx4: lane l's 16 bytes land at the buffer
+// base + 16 l), with no registers and no LDS store instructions.
+#ifndef DPSO_2OPT_DMA
+#define DPSO_2OPT_DMA 1
+#endif
 
 namespace {
 
@@ -151,6 +157,29 @@ __device__ inline int rotate_up(int v)  // lane l receives lane l-1 (lane 0: lan
 }
 
 __device__ inline void compiler_fence() { __asm__ __volatile__("" ::: "memory"); }
+
+constexpr bool kDma = DPSO_2OPT_DMA != 0;
+
+// s_waitcnt immediates (vmcnt in bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8)
+__device__ inline void wait_vmem() { __builtin_amdgcn_s_waitcnt(0x0F70); }  // vmcnt(0)
+__device__ inline void wait_lds() { __builtin_amdgcn_s_waitcnt(0xC07F); }   // lgkmcnt(0)
+
+// A row of n ints (n a multiple of 4) from memory into an LDS buffer of
+// 256 R ints: chunk k of 64 x 16 bytes lands at dst + 256 k. Chunk indices
+// are clamped to the row, so lanes past its end repeat the last chunk into
+// the buffer's tail.
+template <int R>
+__device__ inline void dma_row(const int32_t *src, int n, int32_t *dst)
+{
+    typedef __attribute__((address_space(1))) const void GV;
+    typedef __attribute__((address_space(3))) void LV;
+    const int lane = threadIdx.x, q = (n >> 2) - 1;
+    compiler_fence();
+#pragma unroll
+    for (int k = 0; k < R; ++k)
+        __builtin_amdgcn_global_load_lds((GV *)(src + 4 * min(lane + 64 * k, q)), (LV *)(dst + 256 * k), 16, 0, 0);
+    compiler_fence();
+}
 
 // Row buffers: two per wave, each BS ints. Rows that do not start on 16
 // bytes spill up to 3 ints before and after a buffer, so those kernels keep
@@ -258,11 +287,23 @@ __device__ __forceinline__ void sweep_row(SweepState<MB, VEC4> &S, const int32_t
     int32_t *cur = bufs + BI * ST;
     const int32_t *prv = bufs + (1 - BI) * ST;
     const int lane = threadIdx.x;
-    constexpr int P = kPrefetch == 2 ? BI : 0;
-    S.pipe[P].store(cur, n);  // row of x_i+1, loaded kPrefetch rows ago
-    if (i + kPrefetch + 3 <= n) S.pipe[P].load(D + size_t(tour[i + 1 + kPrefetch]) * n, n);
-    compiler_fence();
-    const int ei = prv[tour[i + 1]];           // D[x_i][x_i+1]
+    int ei;
+    if constexpr (kDma && VEC4) {
+        // the row of x_i+1 went into cur one row ago; once it has landed and
+        // D[x_i][x_i+1] has been read, prv takes the row of x_i+2
+        wait_vmem();
+        compiler_fence();
+        ei = prv[tour[i + 1]];
+        wait_lds();
+        if (i + 4 <= n)
+            dma_row<WaveCfg<MB, VEC4>::RV>(D + size_t(tour[i + 2]) * n, n, bufs + (1 - BI) * ST);
+    } else {
+        constexpr int P = kPrefetch == 2 ? BI : 0;
+        S.pipe[P].store(cur, n);  // row of x_i+1, loaded kPrefetch rows ago
+        if (i + kPrefetch + 3 <= n) S.pipe[P].load(D + size_t(tour[i + 1 + kPrefetch]) * n, n);
+        compiler_fence();
+        ei = prv[tour[i + 1]];                 // D[x_i][x_i+1]
+    }
     int carry = M0 > 0 ? rotate_up(S.g[M0 > 0 ? M0 - 1 : 0]) : 0;
     int rm = kNone;
 #pragma unroll
@@ -337,14 +378,24 @@ __device__ __forceinline__ void twoopt_wave_body(const Inst &I, int p)
             }
         }
         // g <- D[x_0][x_c+1]: the first term of row 0, one column to the right
-        S.pipe[0].load(D + size_t(tour[0]) * n, n);
-        S.pipe[0].store(bufs + ST, n);
-        compiler_fence();
+        if constexpr (kDma && VEC4) {
+            wait_lds();  // earlier reads of both buffers are done
+            dma_row<WaveCfg<MB, VEC4>::RV>(D + size_t(tour[0]) * n, n, bufs + ST);
+            wait_vmem();
+            compiler_fence();
 #pragma unroll
-        for (int m = 0; m < MB; ++m) S.g[m] = lds_word(bufs + ST, S.off(m));
+            for (int m = 0; m < MB; ++m) S.g[m] = lds_word(bufs + ST, S.off(m));
+            dma_row<WaveCfg<MB, VEC4>::RV>(D + size_t(tour[1]) * n, n, bufs);
+        } else {
+            S.pipe[0].load(D + size_t(tour[0]) * n, n);
+            S.pipe[0].store(bufs + ST, n);
+            compiler_fence();
 #pragma unroll
-        for (int k = 0; k < kPrefetch; ++k)
-            if (k + 1 < n) S.pipe[k].load(D + size_t(tour[k + 1]) * n, n);
+            for (int m = 0; m < MB; ++m) S.g[m] = lds_word(bufs + ST, S.off(m));
+#pragma unroll
+            for (int k = 0; k < kPrefetch; ++k)
+                if (k + 1 < n) S.pipe[k].load(D + size_t(tour[k + 1]) * n, n);
+        }
         S.best = kNone;
         S.best_i = 0;
         sweep_phase<MB, VEC4, 0>(S, D, bufs, tour, n);
