@@ -164,12 +164,16 @@ constexpr bool kDma = DPSO_2OPT_DMA != 0;
 __device__ inline void wait_vmem() { __builtin_amdgcn_s_waitcnt(0x0F70); }  // vmcnt(0)
 __device__ inline void wait_lds() { __builtin_amdgcn_s_waitcnt(0xC07F); }   // lgkmcnt(0)
 
+// LDS-address-space view of the row buffers (taken from the shared array
+// itself, so no generic pointer is converted back).
+typedef __attribute__((address_space(3))) int32_t lds_int;
+
 // A row of n ints (n a multiple of 4) from memory into an LDS buffer of
 // 256 R ints: chunk k of 64 x 16 bytes lands at dst + 256 k. Chunk indices
 // are clamped to the row, so lanes past its end repeat the last chunk into
 // the buffer's tail.
 template <int R>
-__device__ inline void dma_row(const int32_t *src, int n, int32_t *dst)
+__device__ inline void dma_row(const int32_t *src, int n, lds_int *dst)
 {
     typedef __attribute__((address_space(1))) const void GV;
     typedef __attribute__((address_space(3))) void LV;
@@ -281,7 +285,7 @@ __device__ inline int lds_word(const int32_t *base, int byte_off)
 // Row i with the first active block M0 and buffer BI (0 for even rows).
 template <int MB, bool VEC4, int M0, int BI>
 __device__ __forceinline__ void sweep_row(SweepState<MB, VEC4> &S, const int32_t *__restrict__ D,
-                                          int32_t *bufs, const uint16_t *tour, int n, int i)
+                                          int32_t *bufs, lds_int *lbufs, const uint16_t *tour, int n, int i)
 {
     constexpr int ST = WaveCfg<MB, VEC4>::STRIDE;
     int32_t *cur = bufs + BI * ST;
@@ -289,14 +293,22 @@ __device__ __forceinline__ void sweep_row(SweepState<MB, VEC4> &S, const int32_t
     const int lane = threadIdx.x;
     int ei;
     if constexpr (kDma && VEC4) {
-        // the row of x_i+1 went into cur one row ago; once it has landed and
-        // D[x_i][x_i+1] has been read, prv takes the row of x_i+2
+        // e_i = D[x_i][x_i+1] and the label x_i+2 come from the registers of
+        // the lanes owning columns i and i + 1 (in this phase, blocks M0 - 1
+        // or M0), not from LDS. The row of x_i+1 went into cur one row ago;
+        // once it has landed, prv (read by the previous row) takes the row of
+        // x_i+2.
+        constexpr int MP = M0 > 0 ? M0 - 1 : 0;
+        const int ne_lo = __builtin_amdgcn_readlane(S.ne[MP], i & 63);
+        const int ne_hi = __builtin_amdgcn_readlane(S.ne[M0], i & 63);
+        ei = -((M0 > 0 && (i >> 6) < M0) ? ne_lo : ne_hi);
+        const int of_lo = __builtin_amdgcn_readlane(S.off(MP), (i + 1) & 63);
+        const int of_hi = __builtin_amdgcn_readlane(S.off(M0), (i + 1) & 63);
+        const int label = ((M0 > 0 && ((i + 1) >> 6) < M0) ? of_lo : of_hi) >> 2;  // x_i+2
         wait_vmem();
-        compiler_fence();
-        ei = prv[tour[i + 1]];
         wait_lds();
-        if (i + 4 <= n)
-            dma_row<WaveCfg<MB, VEC4>::RV>(D + size_t(tour[i + 2]) * n, n, bufs + (1 - BI) * ST);
+        compiler_fence();
+        if (i + 4 <= n) dma_row<WaveCfg<MB, VEC4>::RV>(D + size_t(label) * n, n, lbufs + (1 - BI) * ST);
     } else {
         constexpr int P = kPrefetch == 2 ? BI : 0;
         S.pipe[P].store(cur, n);  // row of x_i+1, loaded kPrefetch rows ago
@@ -327,16 +339,16 @@ __device__ __forceinline__ void sweep_row(SweepState<MB, VEC4> &S, const int32_t
 // Rows [64 M0 - 2, 64 M0 + 62) clipped to [0, n - 2), then the next phase.
 template <int MB, bool VEC4, int M0>
 __device__ __forceinline__ void sweep_phase(SweepState<MB, VEC4> &S, const int32_t *__restrict__ D,
-                                            int32_t *bufs, const uint16_t *tour, int n)
+                                            int32_t *bufs, lds_int *lbufs, const uint16_t *tour, int n)
 {
     const int lo = M0 == 0 ? 0 : 64 * M0 - 2;
     const int hi = min(64 * M0 + 62, n - 2);
     for (int i = lo; i < hi; i += 2) {  // lo is even: row parity picks the buffer
-        sweep_row<MB, VEC4, M0, 0>(S, D, bufs, tour, n, i);
-        if (i + 1 < hi) sweep_row<MB, VEC4, M0, 1>(S, D, bufs, tour, n, i + 1);
+        sweep_row<MB, VEC4, M0, 0>(S, D, bufs, lbufs, tour, n, i);
+        if (i + 1 < hi) sweep_row<MB, VEC4, M0, 1>(S, D, bufs, lbufs, tour, n, i + 1);
     }
     if constexpr (M0 + 1 < MB) {
-        if (hi < n - 2) sweep_phase<MB, VEC4, M0 + 1>(S, D, bufs, tour, n);
+        if (hi < n - 2) sweep_phase<MB, VEC4, M0 + 1>(S, D, bufs, lbufs, tour, n);
     }
 }
 
@@ -355,6 +367,7 @@ __device__ __forceinline__ void twoopt_wave_body(const Inst &I, int p)
     extern __shared__ __align__(16) unsigned char smem[];
     // [guard][buffer 0][guard][buffer 1][guard], buffer k at GU + k * ST
     int32_t *bufs = reinterpret_cast<int32_t *>(smem) + GU;
+    lds_int *lbufs = (lds_int *)smem + GU;  // C-style: an address-space conversion
     uint16_t *tour = reinterpret_cast<uint16_t *>(bufs + 2 * ST);
     uint16_t *xg = st.X + size_t(p) * ns;
     for (int k = lane; k < n; k += 64) tour[k] = xg[k];
@@ -380,12 +393,12 @@ __device__ __forceinline__ void twoopt_wave_body(const Inst &I, int p)
         // g <- D[x_0][x_c+1]: the first term of row 0, one column to the right
         if constexpr (kDma && VEC4) {
             wait_lds();  // earlier reads of both buffers are done
-            dma_row<WaveCfg<MB, VEC4>::RV>(D + size_t(tour[0]) * n, n, bufs + ST);
+            dma_row<WaveCfg<MB, VEC4>::RV>(D + size_t(tour[0]) * n, n, lbufs + ST);
             wait_vmem();
             compiler_fence();
 #pragma unroll
             for (int m = 0; m < MB; ++m) S.g[m] = lds_word(bufs + ST, S.off(m));
-            dma_row<WaveCfg<MB, VEC4>::RV>(D + size_t(tour[1]) * n, n, bufs);
+            dma_row<WaveCfg<MB, VEC4>::RV>(D + size_t(tour[1]) * n, n, lbufs);
         } else {
             S.pipe[0].load(D + size_t(tour[0]) * n, n);
             S.pipe[0].store(bufs + ST, n);
@@ -398,7 +411,7 @@ __device__ __forceinline__ void twoopt_wave_body(const Inst &I, int p)
         }
         S.best = kNone;
         S.best_i = 0;
-        sweep_phase<MB, VEC4, 0>(S, D, bufs, tour, n);
+        sweep_phase<MB, VEC4, 0>(S, D, bufs, lbufs, tour, n);
         // best (delta, i) of the wave, smallest i on ties
         const uint64_t key = (uint64_t(uint32_t(S.best) + 0x80000000u) << 32) | uint32_t(S.best_i);
         const uint64_t win = wave_min_u64(key);
