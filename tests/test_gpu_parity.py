@@ -181,6 +181,15 @@ EDGE = [
     ("stall_limit", 20, 16, 60, dict(stall_limit=3)),
     ("w1_phi04", 50, 100, 12, dict(w=1.0, phi1=0.4, phi2=0.4)),
     ("coef_max", 50, 30, 9, dict(w=2.0, phi1=2.0, phi2=2.0)),
+    # n a multiple of 4: rows staged straight into LDS, at every register-block
+    # class and its edges
+    ("n8_aligned", 8, 9, 9, dict(ee_trigger=2)),
+    ("n68_aligned", 68, 20, 9, dict(ee_trigger=2)),
+    ("n256_aligned", 256, 16, 6, dict(ee_trigger=2)),
+    ("n260_aligned", 260, 16, 6, dict(ee_trigger=2)),
+    ("n512_aligned", 512, 12, 5, dict(ee_trigger=2)),
+    ("n516_aligned", 516, 12, 4, dict(ee_trigger=2)),
+    ("n1024_aligned", 1024, 8, 3, dict(ee_trigger=2)),
 ]
 
 
@@ -364,6 +373,7 @@ BATCH = [
     (127, 9, dict(mutation_period=0)), (128, 6, dict(ee_trigger=2, ee_max_moves=0)),
     (200, 20, {}), (257, 7, dict(ee_trigger=2)), (515, 6, dict(ee_trigger=2)),
     (1000, 5, dict(ee_trigger=2)), (1030, 3, dict(ee_trigger=2)),
+    (260, 6, dict(ee_trigger=2)), (512, 5, dict(ee_trigger=2)), (1024, 3, dict(ee_trigger=2)),
     (50, 10, dict(stall_limit=2)), (40, 10, dict(ee_trigger=0)),
     # paper-literal variants in the same batch as the default instances
     (45, 10, dict(ee_neighbourhood=1, ee_trigger=2)), (2, 4, dict(ee_neighbourhood=1, ee_trigger=2)),
