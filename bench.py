@@ -407,7 +407,8 @@ def main():
     from paper_1706_04399_amd import dpso, scenes
 
     sc, prm = scenes.workload(3)
-    prm = dict(prm, max_generations=args.warmup + args.steps)
+    phase_gens = min(args.steps, 100)          # the untimed phase breakdown afterwards
+    prm = dict(prm, max_generations=args.warmup + args.steps + phase_gens)
     n, S = sc.n, prm["swarm_size"]
     D = dpso.build_dist(sc)
     state = dpso.init_nn(D, prm)
@@ -418,7 +419,7 @@ def main():
     start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     start.record()
-    phases = dpso.run_profiled(D, prm, state, args.steps)
+    timed = dpso.run_timed(D, prm, state, args.steps)   # events around the exchange launches only
     end.record()
     torch.cuda.synchronize()
     ms = start.elapsed_time(end)
@@ -428,8 +429,8 @@ def main():
 
     sweeps = info1["sweeps"] - info0["sweeps"]
     bytes_per_sweep = 4 * n * (n - 3) + 4 * n     # two gathers per exchange + edge costs
-    launches = phases["exchange_launches"]
-    avg_launch_s = phases["ms_exchange"] / launches / 1e3
+    launches = timed["exchange_launches"]
+    avg_launch_s = timed["ms_exchange"] / launches / 1e3
     achieved = sweeps / launches * bytes_per_sweep / avg_launch_s / 1e9
     tb = hbm_traffic_per_launch()
     traffic = round(tb / avg_launch_s / 1e9, 2) if tb is not None else None
@@ -448,9 +449,14 @@ def main():
         "roofline": {"bound": "hbm", "kernel": exchange_kernel_name(n),
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic},
-        "phases_ms": {k: round(v, 2) for k, v in phases.items() if k.startswith("ms_")},
+        "exchange_ms_per_launch": round(avg_launch_s * 1e3, 4),
         "best_cost_mm": info1["best_cost"],
     }
+    # device time per generation of each phase, from a profiled run after the
+    # timed region (its events between phases add a little time of their own)
+    phases = dpso.run_profiled(D, prm, state, phase_gens)
+    line["phases_ms_per_generation"] = {k[3:]: round(v / phase_gens, 4) for k, v in phases.items()
+                                        if k.startswith("ms_")}
     # the distance builder, timed on its own after the timed region: median of 5
     build_ms = []
     for _ in range(6):

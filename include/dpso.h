@@ -265,9 +265,12 @@ typedef struct {
     float ms_total;     /* first to last event                                 */
     float ms_move;      /* velocity / position update, cost, personal best     */
     float ms_mutation;  /* duplicate marking, ranking and reshuffles           */
-    float ms_gbest;     /* both global-best reductions                         */
+    float ms_gbest;     /* both global-best reductions (with the edge exchange
+                           on, the second one also runs the end of the
+                           generation)                                         */
     float ms_exchange;  /* 2-opt edge exchange                                 */
-    float ms_control;   /* end-of-generation step                              */
+    float ms_control;   /* end-of-generation step when it runs on its own (the
+                           edge exchange off), else 0                          */
     int32_t generations;        /* generations enqueued                        */
     int32_t exchange_launches;  /* edge-exchange kernel launches               */
 } dpso_phase_times;
@@ -277,6 +280,15 @@ typedef struct {
 dpso_status dpso_run_profiled(const int32_t *d_dist, int32_t n, const dpso_params *params,
                               void *d_state, size_t state_bytes, int32_t generations,
                               dpso_phase_times *times, void *stream);
+
+/* dpso_run with a HIP event just before and just after every edge-exchange
+ * launch, and no others: times->ms_exchange receives their summed device
+ * time, times->exchange_launches and times->generations the counts, the
+ * other fields 0. Synchronises `stream`. Two events a generation instead of
+ * dpso_run_profiled's six, for timing whole runs with the exchange kernel's
+ * own duration. Results are identical to dpso_run. */
+dpso_status dpso_run_timed(const int32_t *d_dist, int32_t n, const dpso_params *params, void *d_state,
+                           size_t state_bytes, int32_t generations, dpso_phase_times *times, void *stream);
 
 /* One swarm of a batch: its own distance matrix, parameters and state. */
 typedef struct {

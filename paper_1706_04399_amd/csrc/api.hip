@@ -294,9 +294,10 @@ hipError_t enqueue_batch(const BatchPlan &P, int32_t generations, hipStream_t s)
         if (P.any_exchange) {
             for (int c = 0; c < dpso::kExchangeClasses && e == hipSuccess; ++c)
                 if (P.cls[c].count > 0) e = dpso::launch_batch_2opt(c, P.cls[c], P.cls_total[c], P.cls_max_ns[c], s);
-            if (e == hipSuccess) e = dpso::launch_batch_gbest(P.items, P.instances, P.total, P.max_ns, 2, s);
+            if (e == hipSuccess) e = dpso::launch_batch_gbest(P.items, P.instances, P.total, P.max_ns, 3, s);
+        } else if (e == hipSuccess) {
+            e = dpso::launch_batch_end(P.items, P.instances, P.total, P.max_ns, s);
         }
-        if (e == hipSuccess) e = dpso::launch_batch_end(P.items, P.instances, P.total, P.max_ns, s);
     }
     return e;
 }
@@ -317,8 +318,11 @@ dpso_status events(size_t count, std::vector<hipEvent_t> &out)
     return DPSO_OK;
 }
 
+// times: events between every phase; exchange_only: events around the
+// edge-exchange launches only (their summed time into times->ms_exchange).
 dpso_status run_impl(const int32_t *d_dist, int32_t n, const dpso_params *params, void *d_state,
-                     size_t state_bytes, int32_t generations, void *stream, dpso_phase_times *times)
+                     size_t state_bytes, int32_t generations, void *stream, dpso_phase_times *times,
+                     bool exchange_only = false)
 {
     dpso_status st = check_params(params, n);
     if (st) return st;
@@ -332,9 +336,13 @@ dpso_status run_impl(const int32_t *d_dist, int32_t n, const dpso_params *params
     hipStream_t s = as_stream(stream);
     std::vector<hipEvent_t> ev;
     constexpr int kMarks = 6;  // after move, mutation, gbest, exchange, gbest, end
-    if (times && (st = events(size_t(generations) * kMarks + 1, ev))) return st;
+    const bool all = times && !exchange_only;
+    const bool ex = times && exchange_only && kp.ee_trigger != DPSO_EE_OFF;
+    if (all && (st = events(size_t(generations) * kMarks + 1, ev))) return st;
+    if (ex && (st = events(size_t(generations) * 2, ev))) return st;
     size_t mark = 0;
-    auto stamp = [&]() -> hipError_t { return times ? hipEventRecord(ev[mark++], s) : hipSuccess; };
+    auto stamp = [&]() -> hipError_t { return all ? hipEventRecord(ev[mark++], s) : hipSuccess; };
+    auto stamp_ex = [&]() -> hipError_t { return ex ? hipEventRecord(ev[mark++], s) : hipSuccess; };
     HIP_TRY(dpso::launch_check(I, s), "launch check");
     HIP_TRY(stamp(), "record event");
     for (int32_t g = 0; g < generations; ++g) {
@@ -344,14 +352,29 @@ dpso_status run_impl(const int32_t *d_dist, int32_t n, const dpso_params *params
         HIP_TRY(stamp(), "record event");
         HIP_TRY(dpso::launch_gbest(I, 1, s), "launch gbest");
         HIP_TRY(stamp(), "record event");
+        HIP_TRY(stamp_ex(), "record event");
         if (kp.ee_trigger != DPSO_EE_OFF) HIP_TRY(dpso::launch_2opt(I, s), "launch 2-opt");
         HIP_TRY(stamp(), "record event");
-        if (kp.ee_trigger != DPSO_EE_OFF) HIP_TRY(dpso::launch_gbest(I, 2, s), "launch gbest");
+        HIP_TRY(stamp_ex(), "record event");
+        // with the exchange on, the end of the generation runs in the global
+        // best's launch (the control phase then times nothing)
+        if (kp.ee_trigger != DPSO_EE_OFF) HIP_TRY(dpso::launch_gbest(I, 3, s), "launch gbest");
         HIP_TRY(stamp(), "record event");
-        HIP_TRY(dpso::launch_end(I, s), "launch end");
+        if (kp.ee_trigger == DPSO_EE_OFF) HIP_TRY(dpso::launch_end(I, s), "launch end");
         HIP_TRY(stamp(), "record event");
     }
-    if (times) {
+    if (times && exchange_only) {
+        HIP_TRY(hipStreamSynchronize(s), "synchronise stream");
+        dpso_phase_times t{};
+        for (size_t i = 0; i + 1 < mark; i += 2) {
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, ev[i], ev[i + 1]), "event time");
+            t.ms_exchange += ms;
+        }
+        t.generations = generations;
+        t.exchange_launches = kp.ee_trigger != DPSO_EE_OFF ? generations : 0;
+        *times = t;
+    } else if (times) {
         HIP_TRY(hipStreamSynchronize(s), "synchronise stream");
         dpso_phase_times t{};
         float *slot[kMarks] = {&t.ms_move, &t.ms_mutation, &t.ms_gbest,
@@ -461,6 +484,13 @@ dpso_status dpso_run_profiled(const int32_t *d_dist, int32_t n, const dpso_param
 {
     if (!times) return fail(DPSO_E_INVAL, "times is NULL");
     return run_impl(d_dist, n, params, d_state, state_bytes, generations, stream, times);
+}
+
+dpso_status dpso_run_timed(const int32_t *d_dist, int32_t n, const dpso_params *params, void *d_state,
+                           size_t state_bytes, int32_t generations, dpso_phase_times *times, void *stream)
+{
+    if (!times) return fail(DPSO_E_INVAL, "times must be non-NULL");
+    return run_impl(d_dist, n, params, d_state, state_bytes, generations, stream, times, true);
 }
 
 dpso_status dpso_get_info(const void *d_state, dpso_info *info, void *stream)

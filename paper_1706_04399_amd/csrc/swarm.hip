@@ -795,6 +795,15 @@ __device__ __forceinline__ void end_body(const Inst &I)
 // Each body runs as a single-instance kernel (descriptor by value) and as a
 // batched kernel over many instances (descriptor from a device table).
 
+// The global best after the exchange, then the end of the generation, in one
+// launch (every early return of the first part is uniform over the block).
+__device__ __forceinline__ void gbest2_end_body(const Inst &I)
+{
+    gbest_body<2>(I);
+    __syncthreads();
+    if (threadIdx.x == 0) end_body(I);
+}
+
 #define DPSO_KERNELS(name, threads, call)                                                   \
     __global__ __launch_bounds__(threads) void name(Inst I)                                  \
     {                                                                                        \
@@ -823,6 +832,7 @@ DPSO_KERNELS(k_gbest0, 1024, gbest_body<0>(I))
 DPSO_KERNELS(k_gbest1, 1024, gbest_body<1>(I))
 DPSO_KERNELS(k_gbest2, 1024, gbest_body<2>(I))
 DPSO_KERNELS(k_end, 64, end_body(I))
+DPSO_KERNELS(k_gbest2_end, 1024, gbest2_end_body(I))
 
 #undef DPSO_KERNELS
 
@@ -907,7 +917,8 @@ hipError_t launch_gbest_t(const Target &t, int mode, hipStream_t s)
 {
     if (mode == 0) return launch(k_gbest0, k_gbest0_batch, t, false, 1024, 0, s);
     if (mode == 1) return launch(k_gbest1, k_gbest1_batch, t, false, 1024, 0, s);
-    return launch(k_gbest2, k_gbest2_batch, t, false, 1024, 0, s);
+    if (mode == 2) return launch(k_gbest2, k_gbest2_batch, t, false, 1024, 0, s);
+    return launch(k_gbest2_end, k_gbest2_end_batch, t, false, 1024, 0, s);  // 3: mode 2, then the end
 }
 
 hipError_t launch_end_t(const Target &t, hipStream_t s)

@@ -96,6 +96,8 @@ EXPORTS = {
                              C.c_int32, C.c_void_p]),
     "dpso_run_profiled": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_size_t,
                                       C.c_int32, C.c_void_p, C.c_void_p]),
+    "dpso_run_timed": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_size_t,
+                                      C.c_int32, C.c_void_p, C.c_void_p]),
     "dpso_batch_work_bytes": (C.c_size_t, [C.c_int32]),
     "dpso_init_batch": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p]),
     "dpso_run_batch": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_size_t,
@@ -237,6 +239,17 @@ def run_profiled(D: torch.Tensor, params, state: torch.Tensor, generations: int,
     _check(lib().dpso_run_profiled(_dev(D, torch.int32), n, C.byref(_params(params)),
                                    _dev(state, torch.uint8), state.numel(), int(generations),
                                    C.byref(t), _stream(stream)))
+    return {k: getattr(t, k) for k, _ in PhaseTimes._fields_}
+
+
+def run_timed(D: torch.Tensor, params, state: torch.Tensor, generations: int, stream=None) -> dict:
+    """run() with HIP events around the edge-exchange launches only; returns
+    their summed device ms (the other phase fields are 0)."""
+    n = D.shape[0]
+    t = PhaseTimes()
+    _check(lib().dpso_run_timed(_dev(D, torch.int32), n, C.byref(_params(params)),
+                                _dev(state, torch.uint8), state.numel(), int(generations),
+                                C.byref(t), _stream(stream)))
     return {k: getattr(t, k) for k, _ in PhaseTimes._fields_}
 
 

@@ -355,6 +355,32 @@ def test_split_run_equals_single_run(dp):
         assert np.array_equal(ea["V"][p, :L], eb["V"][p, :L]), p
 
 
+@pytest.mark.parametrize("trigger", [0, 1, 2])
+def test_timed_and_profiled_runs_equal_plain_runs(dp, trigger):
+    """The two timing entry points leave the same state as dpso_run, and count
+    one exchange launch a generation when the exchange is on."""
+    sc, prm = scenes.workload(1)
+    prm = dict(prm, ee_trigger=trigger)
+    note(f"timed runs, trigger {trigger}")
+    Dg = _dev(oracle.build_dist(sc))
+    states = []
+    for how in ("plain", "timed", "profiled"):
+        st = dp.init_nn(Dg, prm)
+        if how == "plain":
+            dp.run(Dg, prm, st, 25)
+        elif how == "timed":
+            t = dp.run_timed(Dg, prm, st, 25)
+            assert t["exchange_launches"] == (25 if trigger else 0) and t["generations"] == 25
+            assert (t["ms_exchange"] > 0) == (trigger != 0) and t["ms_move"] == 0
+        else:
+            t = dp.run_profiled(Dg, prm, st, 25)
+            assert t["ms_move"] > 0 and t["generations"] == 25
+        states.append(dp.export_state(st, sc.n, prm["swarm_size"]))
+    for other in states[1:]:
+        for k in ("X", "P", "F", "FP", "G", "vlen", "trace"):
+            assert np.array_equal(np.asarray(states[0][k]), np.asarray(other[k])), k
+
+
 def test_state_mismatch_is_reported(dp):
     sc, prm = scenes.workload(1)
     D = oracle.build_dist(sc)
