@@ -253,8 +253,10 @@ constexpr uint16_t kEmit = 1u << 14;   // in rho[p]: p is not the largest of its
 constexpr uint16_t kFixed = 1u << 15;  // in rho[p]: p is among the first k of those
 constexpr uint16_t kLabel = 0x0fff;    // labels and positions (n <= 4096)
 
-// LDS of one particle (ns = n rounded up to 64): eight uint16 arrays and
-// two uint32 pointer-jumping buffers, 24 ns bytes.
+// LDS of one particle (nl = n rounded up to 8): six uint16 arrays and two
+// uint32 pointer-jumping buffers, 20 nl bytes. from / posf (the stored
+// velocity's tours, used first) and x / posx (used after) share slots, so
+// eight 1000-viewpoint particles fit in a CU's LDS.
 struct MoveLds {
     uint16_t *x, *posx, *from, *posf, *to, *rho, *cur, *z;
     uint32_t *e0, *e1;
@@ -278,18 +280,20 @@ __device__ inline bool vote_any(MoveLds &L, bool pred)
     return any;
 }
 
-__device__ MoveLds carve_move_lds(unsigned char *base, int ns)
+__device__ MoveLds carve_move_lds(unsigned char *base, int nl)
 {
     MoveLds L;
     uint16_t *u = reinterpret_cast<uint16_t *>(base);
-    uint16_t **slots[] = {&L.x, &L.posx, &L.from, &L.posf, &L.to, &L.rho, &L.cur, &L.z};
+    uint16_t **slots[] = {&L.x, &L.posx, &L.to, &L.rho, &L.cur, &L.z};
     for (uint16_t **s : slots) {
         *s = u;
-        u += ns;
+        u += nl;
     }
-    L.e0 = reinterpret_cast<uint32_t *>(u);
-    L.e1 = L.e0 + ns;
-    L.wsum = reinterpret_cast<int *>(L.e1 + ns);
+    L.from = L.x;
+    L.posf = L.posx;
+    L.e0 = reinterpret_cast<uint32_t *>(u);  // 12 nl bytes in: 16-byte aligned
+    L.e1 = L.e0 + nl;
+    L.wsum = reinterpret_cast<int *>(L.e1 + nl);
     L.vote = L.wsum + 4;
     L.round = 0;
     return L;
@@ -435,7 +439,12 @@ __device__ inline int prefix_count(uint64_t coef_q16, uint64_t r16, int len)
 
 }  // namespace
 
-size_t move_lds_bytes(int ns) { return size_t(ns) * 2 * 8 + size_t(ns) * 4 * 2 + 64; }  // + sums, votes
+// The default move's arrays (+ sums, votes) or the raw-velocity move's 15 ns.
+size_t move_lds_bytes(int n, int ns)
+{
+    const size_t nl = (size_t(n) + 7) & ~size_t(7);
+    return std::max(nl * 2 * 6 + nl * 4 * 2 + 64, size_t(ns) * 15);
+}
 
 // The move with the velocity kept as the raw concatenation of eq. velocity
 // (velocity_cap > 0): y as in the default move, and the new velocity is the
@@ -566,7 +575,7 @@ __device__ __forceinline__ void move_body(const Inst &I, int part)
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int64_t redi[kMoveThreads / 64];
     __shared__ uint64_t draw0;  // first 64-bit word of stream (part, t, vel)
-    MoveLds L = carve_move_lds(smem, ns);
+    MoveLds L = carve_move_lds(smem, (n + 7) & ~7);
     if (tid < 3) L.vote[tid] = 0;  // ordered before the first vote by the barriers below
 
     const uint16_t *xg = st.X + size_t(part) * ns;
@@ -574,11 +583,8 @@ __device__ __forceinline__ void move_body(const Inst &I, int part)
     const bool has_v = st.VL[part] != 0;
     DPSO_EACH(k)
     {
-        const uint16_t v = xg[k];
-        L.x[k] = v;
-        L.z[k] = v;
-        L.posx[v] = uint16_t(k);
-        if (has_v) {
+        L.z[k] = xg[k];
+        if (has_v) {  // the stored velocity's tours, in the slots x / posx take later
             const uint16_t f = vref[k];
             L.from[k] = f;
             L.posf[f] = uint16_t(k);
@@ -602,8 +608,15 @@ __device__ __forceinline__ void move_body(const Inst &I, int part)
                             },
                             whole_w, L);
         DPSO_EACH(k) L.z[k] = L.cur[L.posf[L.z[k]]];
+        __syncthreads();  // posf is read above; posx takes its slot now
     }
-    DPSO_EACH(k) L.to[k] = st.P[size_t(part) * ns + k];
+    DPSO_EACH(k)
+    {
+        const uint16_t v = xg[k];
+        L.x[k] = v;
+        L.posx[v] = uint16_t(k);
+        L.to[k] = st.P[size_t(part) * ns + k];
+    }
     __syncthreads();
     // z <- b(z), b the prefix of P - x
     partial_toward<EPT>(L.x, L.posx, L.to, n, [&](int len) { return prefix_count(kp.phi1_q16, r1, len); },
@@ -896,7 +909,8 @@ hipError_t launch_check_t(const Target &t, hipStream_t s)
 
 hipError_t launch_move_t(const Target &t, hipStream_t s)
 {
-    const size_t lds = move_lds_bytes(t.max_ns);
+    // a single instance sizes LDS by its n; a batch by its largest row stride
+    const size_t lds = t.one ? move_lds_bytes(t.one->st.n, t.one->st.ns) : move_lds_bytes(t.max_ns, t.max_ns);
     const int ept = (t.max_ns + kMoveThreads - 1) / kMoveThreads;
     if (ept <= 1) return launch(k_move1, k_move1_batch, t, true, kMoveThreads, lds, s);
     if (ept <= 2) return launch(k_move2, k_move2_batch, t, true, kMoveThreads, lds, s);
