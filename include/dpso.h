@@ -15,7 +15,8 @@
  *    return to the first node is implicit.
  *  - Distances are int32 millimetres, row-major [n][n], symmetric, zero on
  *    the diagonal, 0 <= d < DPSO_D_INF, or DPSO_D_INF for a pair with no
- *    obstacle-free path (the paper's "very large cost", Sect. 2.3). Costs are
+ *    obstacle-free path (Sect. 2.3 gives such a pair an arbitrarily large
+ *    cost). Costs are
  *    int64.
  *  - Pointers prefixed d_ are device memory on the current HIP device; h_
  *    pointers and dpso_scene arrays are host memory. The caller owns every

@@ -745,7 +745,7 @@ __device__ __forceinline__ void mut_apply_body(const Inst &I, int p)
     }
 }
 
-// Global best (pseudo code: "find the particle with the best fitness"): the
+// Global best (the pseudo code's step that picks the fittest particle): the
 // minimum of the packed key (FP << 16 | p) gives the cheapest personal best
 // with the lowest index on ties. mode 0 (initialisation) installs it
 // unconditionally; mode 1 (after move and mutation) and mode 2 (after the
