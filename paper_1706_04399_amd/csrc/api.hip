@@ -286,6 +286,8 @@ dpso_status plan_batch(const dpso_batch_item *items, int32_t count, void *d_work
 hipError_t enqueue_batch(const BatchPlan &P, int32_t generations, hipStream_t s)
 {
     hipError_t e = dpso::launch_batch_check(P.items, P.instances, P.total, P.max_ns, s);
+    for (int c = 0; c < dpso::kExchangeClasses && e == hipSuccess && P.any_exchange; ++c)
+        e = dpso::launch_batch_2opt_prepare(c, P.cls[c], P.cls_max_ns[c], s);
     for (int32_t g = 0; g < generations && e == hipSuccess; ++g) {
         e = dpso::launch_batch_move(P.items, P.instances, P.total, P.max_ns, s);
         if (e == hipSuccess && P.any_mutation)
@@ -344,6 +346,7 @@ dpso_status run_impl(const int32_t *d_dist, int32_t n, const dpso_params *params
     auto stamp = [&]() -> hipError_t { return all ? hipEventRecord(ev[mark++], s) : hipSuccess; };
     auto stamp_ex = [&]() -> hipError_t { return ex ? hipEventRecord(ev[mark++], s) : hipSuccess; };
     HIP_TRY(dpso::launch_check(I, s), "launch check");
+    if (kp.ee_trigger != DPSO_EE_OFF) HIP_TRY(dpso::launch_2opt_prepare(I, s), "launch exchange set-up");
     HIP_TRY(stamp(), "record event");
     for (int32_t g = 0; g < generations; ++g) {
         HIP_TRY(dpso::launch_move(I, s), "launch move");

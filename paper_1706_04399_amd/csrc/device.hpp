@@ -158,6 +158,7 @@ __device__ inline Inst batch_pick(const Batch &B, int b, int &local)
     v.F = global_ptr(v.F);
     v.FP = global_ptr(v.FP);
     v.trace = global_ptr(v.trace);
+    v.H = global_ptr(v.H);
     return I;
 }
 

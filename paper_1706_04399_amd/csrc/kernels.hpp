@@ -29,10 +29,15 @@ hipError_t launch_batch_end(const Batch &items, const Batch &instances, int tota
 // twoopt.hip: the edge-exchange kernel depends on the neighbourhood, on n
 // (columns held per lane) and on the alignment of D; instances of one class
 // share a launch. The last class is the node-swap neighbourhood.
-constexpr int kExchangeClasses = 12;
+constexpr int kExchangeClasses = 17;
 int exchange_class(int n, const int32_t *D, int neighbourhood);
 hipError_t launch_2opt(const Inst &I, hipStream_t s);
 hipError_t launch_batch_2opt(int cls, const Batch &items, int total, int max_ns, hipStream_t s);
+// Per-run set-up of the exchange: classes that stage 16-bit rows refresh the
+// state's packed copy of D (after the run's first launch, which clears the
+// header's maximum). `members` is a class's instance table; max_n bounds n.
+hipError_t launch_2opt_prepare(const Inst &I, hipStream_t s);
+hipError_t launch_batch_2opt_prepare(int cls, const Batch &members, int max_n, hipStream_t s);
 
 // nodeswap.hip: the node-swap neighbourhood (one workgroup per particle).
 hipError_t launch_node_swap(const Inst *one, const Batch &items, int grid, int max_ns, hipStream_t s);

@@ -14,8 +14,12 @@
 //   trace  int64  [cap]     global-best cost after each generation
 //   flags  int32  [S]      mutation scratch: duplicate marks
 //   keep   int32  [S]      mutation scratch: kept marks
+//   H      uint16 [n][n]   D >> shift, the rows the edge exchange stages when
+//                          n is a multiple of 8 and at most 1024 (else empty);
+//                          rewritten by every run
 #pragma once
 
+#include <hip/hip_runtime.h>
 #include <stddef.h>
 #include <stdint.h>
 
@@ -36,11 +40,25 @@ struct Hdr {
     int32_t velocity_cap;  // 0: velocity held as two tours; > 0: as a transposition list
     int64_t FG;        // cost of the global best
     uint64_t n_sweeps, n_moves, n_reshuffled;
+    uint32_t dmax;     // largest entry of D, found at the start of each run
+    int32_t pad;
 };
+
+// The edge exchange stages 16-bit rows (H = D >> shift) for these n: rows of
+// 2n bytes then start on 16 bytes, and a sweep fits one wavefront.
+inline bool packed_rows(int32_t n) { return n >= 8 && n <= 1024 && (n & 7) == 0; }
+
+// shift that brings the largest entry of D under 2^16
+__host__ __device__ inline int pack_shift(uint32_t dmax)
+{
+    int bits = 0;
+    while (bits < 32 && (dmax >> bits) != 0) ++bits;
+    return bits > 16 ? bits - 16 : 0;
+}
 
 struct Layout {
     int32_t n, S, cap, ns;
-    size_t hdr, X, P, V, VL, F, FP, G, trace, flags, keep, total;
+    size_t hdr, X, P, V, VL, F, FP, G, trace, flags, keep, H, total;
 };
 
 inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
@@ -63,6 +81,7 @@ inline Layout make_layout(int32_t n, int32_t S, int32_t cap)
     L.trace = take(size_t(cap) * 8);
     L.flags = take(size_t(S) * 4);
     L.keep = take(size_t(S) * 4);
+    L.H = take(packed_rows(n) ? size_t(n) * n * 2 : 0);
     L.total = o;
     return L;
 }
@@ -72,6 +91,7 @@ struct View {
     Hdr *hdr;
     uint16_t *X, *P, *G;
     uint16_t *V;
+    uint16_t *H;  // packed rows (see Layout), valid when packed_rows(n)
     int32_t *VL, *flags, *keep;
     int64_t *F, *FP, *trace;
     int32_t n, S, ns;
@@ -92,6 +112,7 @@ inline View make_view(void *base, const Layout &L)
     v.trace = reinterpret_cast<int64_t *>(b + L.trace);
     v.flags = reinterpret_cast<int32_t *>(b + L.flags);
     v.keep = reinterpret_cast<int32_t *>(b + L.keep);
+    v.H = reinterpret_cast<uint16_t *>(b + L.H);
     v.n = L.n; v.S = L.S; v.ns = L.ns;
     return v;
 }

@@ -173,6 +173,7 @@ __device__ __forceinline__ void hdr_check_body(const Inst &I)
     if (h->magic != kMagic || h->n != I.st.n || h->S != I.st.S || h->cap != I.cap ||
         (h->velocity_cap > 0) != (I.kp.velocity_cap > 0))
         h->err = 1;
+    if (threadIdx.x == 0) h->dmax = 0;  // the run's packed rows start from here
 }
 
 // One workgroup per particle. Particles below det_count take the

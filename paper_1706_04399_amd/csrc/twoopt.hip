@@ -13,6 +13,8 @@
 // the neighbourhood; the next row is loaded while row i is evaluated
 // (three row buffers in rotation), so each row of D is read from L2 once
 // per sweep.
+#include <algorithm>
+
 #include "device.hpp"
 #include "dpso.h"
 #include "kernels.hpp"
@@ -143,7 +145,26 @@ __device__ __forceinline__ void twoopt_rows_body(const Inst &I, int p)
 #ifndef DPSO_2OPT_DMA
 #define DPSO_2OPT_DMA 1
 #endif
+// Rows staged as 16-bit values (see below) when n is a multiple of 8.
+#ifndef DPSO_2OPT_HALF
+#define DPSO_2OPT_HALF 1
+#endif
 
+// Packed rows. The sweep is bound by staging rows into LDS, 4n bytes each.
+// With H = D >> s, s the smallest shift that brings every entry of D under
+// 2^16 (0 while distances stay below 65.536 m), a row takes 2n bytes. Writing
+// each entry as D = 2^s h + r (h its entry of H, 0 <= r < 2^s), the sum
+//   A(i, j) = H[x_i][x_j] + H[x_i+1][x_j+1] - H[x_i][x_i+1] - H[x_j][x_j+1]
+// gives delta(i, j) = 2^s A(i, j) + rho with |rho| <= 2 (2^s - 1). So the
+// exchange with the smallest delta, and every exchange tying with it, has
+// A <= A_min + T, T = floor(4 (2^s - 1) / 2^s) (0, 2 and 3 for s = 0, 1 and
+// s >= 2), and no exchange improves the tour when 2^s A_min >= 2 (2^s - 1).
+// Each lane keeps, over the rows, the two smallest of its row minima of A
+// with their rows and the third smallest value (branch-free updates). At the
+// end, with A_min the wave's minimum, the rows holding a lane minimum <= A_min
+// + T are evaluated exactly from D and the smallest (delta, i, j) is taken
+// over them; should a lane's third value also be in the window, every row is
+// evaluated exactly. The exchange found is the one the int32 sweep finds.
 namespace {
 
 constexpr int kPrefetch = DPSO_2OPT_PREFETCH;
@@ -159,6 +180,7 @@ __device__ inline int rotate_up(int v)  // lane l receives lane l-1 (lane 0: lan
 __device__ inline void compiler_fence() { __asm__ __volatile__("" ::: "memory"); }
 
 constexpr bool kDma = DPSO_2OPT_DMA != 0;
+constexpr bool kHalf = DPSO_2OPT_HALF != 0 && kDma;
 
 // s_waitcnt immediates (vmcnt in bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8)
 __device__ inline void wait_vmem() { __builtin_amdgcn_s_waitcnt(0x0F70); }  // vmcnt(0)
@@ -185,6 +207,21 @@ __device__ inline void dma_row(const int32_t *src, int n, lds_int *dst)
     compiler_fence();
 }
 
+// A row of n uint16 (n a multiple of 8) into an LDS buffer: chunk k of
+// 64 x 16 bytes lands at byte 1024 k of dst, chunk indices clamped to the row.
+template <int R>
+__device__ inline void dma_half(const uint16_t *src, int n, lds_int *dst)
+{
+    typedef __attribute__((address_space(1))) const void GV;
+    typedef __attribute__((address_space(3))) void LV;
+    const int lane = threadIdx.x, q = (n >> 3) - 1;
+    compiler_fence();
+#pragma unroll
+    for (int k = 0; k < R; ++k)
+        __builtin_amdgcn_global_load_lds((GV *)(src + 8 * min(lane + 64 * k, q)), (LV *)(dst + 256 * k), 16, 0, 0);
+    compiler_fence();
+}
+
 // Row buffers: two per wave, each BS ints. Rows that do not start on 16
 // bytes spill up to 3 ints before and after a buffer, so those kernels keep
 // guard words around each buffer; aligned kernels keep none (10 KiB of LDS
@@ -192,6 +229,7 @@ __device__ inline void dma_row(const int32_t *src, int n, lds_int *dst)
 template <int MB, bool VEC4>
 struct WaveCfg {
     static constexpr int RV = (MB + 3) / 4;  // int4 per lane per aligned row
+    static constexpr int RH = (MB + 7) / 8;  // 16-byte chunks per lane per uint16 row
     static constexpr int RU = (64 * MB + 3 + 255) / 256;  // ... per row starting off 16 B
     static constexpr int BS = 256 * RV;      // row length capacity (ints) >= 64 MB >= n
     static constexpr int GUARD = VEC4 ? 0 : 4;  // ints before and after each buffer
@@ -261,6 +299,9 @@ struct SweepState {
     int g[MB];     // gathers of the previous row
     RowPipe<MB, VEC4> pipe[kPrefetch];  // rows in flight (alternating by row parity)
     int best, best_i;
+    // packed rows: the lane's two smallest row minima of A with their rows,
+    // and its third smallest value
+    int v1, r1, v2, r2, v3;
 
     __device__ inline int off(int m) const
     {
@@ -282,17 +323,47 @@ __device__ inline int lds_word(const int32_t *base, int byte_off)
     return *reinterpret_cast<const int32_t *>(reinterpret_cast<const char *>(base) + byte_off);
 }
 
-// Row i with the first active block M0 and buffer BI (0 for even rows).
-template <int MB, bool VEC4, int M0, int BI>
+// Lane index computed in place: a volatile asm is neither hoisted nor
+// merged, so no register has to hold it across the sweep.
+__device__ inline int lane_here()
+{
+    int v;
+    __asm__ volatile("v_mbcnt_lo_u32_b32 %0, -1, 0\n\tv_mbcnt_hi_u32_b32 %0, -1, %0" : "=v"(v));
+    return v;
+}
+
+__device__ inline int lds_half(const int32_t *base, int byte_off)
+{
+    return *reinterpret_cast<const uint16_t *>(reinterpret_cast<const char *>(base) + byte_off);
+}
+
+// Row i with the first active block M0 and buffer BI (0 for even rows);
+// HALF: rows of H (16-bit) instead of D.
+template <int MB, bool VEC4, bool HALF, int M0, int BI>
 __device__ __forceinline__ void sweep_row(SweepState<MB, VEC4> &S, const int32_t *__restrict__ D,
-                                          int32_t *bufs, lds_int *lbufs, const uint16_t *tour, int n, int i)
+                                          const uint16_t *__restrict__ H, int32_t *bufs, lds_int *lbufs,
+                                          const uint16_t *tour, int n, int i)
 {
     constexpr int ST = WaveCfg<MB, VEC4>::STRIDE;
     int32_t *cur = bufs + BI * ST;
     const int32_t *prv = bufs + (1 - BI) * ST;
     const int lane = threadIdx.x;
     int ei;
-    if constexpr (kDma && VEC4) {
+    if constexpr (HALF) {
+        // as below, with ne holding -H[x_c][x_c+1] and off the byte offset
+        // 2 x_c+1 of a 16-bit row
+        constexpr int MP = M0 > 0 ? M0 - 1 : 0;
+        const int ne_lo = __builtin_amdgcn_readlane(S.ne[MP], i & 63);
+        const int ne_hi = __builtin_amdgcn_readlane(S.ne[M0], i & 63);
+        ei = -((M0 > 0 && (i >> 6) < M0) ? ne_lo : ne_hi);
+        const int of_lo = __builtin_amdgcn_readlane(S.off(MP), (i + 1) & 63);
+        const int of_hi = __builtin_amdgcn_readlane(S.off(M0), (i + 1) & 63);
+        const int label = ((M0 > 0 && ((i + 1) >> 6) < M0) ? of_lo : of_hi) >> 1;  // x_i+2
+        wait_vmem();
+        wait_lds();
+        compiler_fence();
+        if (i + 4 <= n) dma_half<WaveCfg<MB, VEC4>::RH>(H + size_t(label) * n, n, lbufs + (1 - BI) * ST);
+    } else if constexpr (kDma && VEC4) {
         // e_i = D[x_i][x_i+1] and the label x_i+2 come from the registers of
         // the lanes owning columns i and i + 1 (in this phase, blocks M0 - 1
         // or M0), not from LDS. The row of x_i+1 went into cur one row ago;
@@ -323,38 +394,46 @@ __device__ __forceinline__ void sweep_row(SweepState<MB, VEC4> &S, const int32_t
         const int r = rotate_up(S.g[m]);
         const int a = lane == 0 ? carry : r;
         carry = r;
-        const int b = lds_word(cur, S.off(m));
+        const int b = HALF ? lds_half(cur, S.off(m)) : lds_word(cur, S.off(m));
         int d = a + b + S.ne[m];
-        if (m == M0) d = lane + 64 * M0 < i + 2 ? kNone : d;
+        if (m == M0) d = (HALF ? lane_here() : lane) + 64 * M0 < i + 2 ? kNone : d;
         rm = min(rm, d);
         S.g[m] = b;
     }
     const int cand = rm - ei;
-    if (cand < S.best) {
+    if constexpr (HALF) {
+        const bool c1 = cand < S.v1, c2 = cand < S.v2;
+        S.v3 = c2 ? S.v2 : min(S.v3, cand);
+        S.v2 = c1 ? S.v1 : (c2 ? cand : S.v2);
+        S.r2 = c1 ? S.r1 : (c2 ? i : S.r2);
+        S.v1 = min(S.v1, cand);
+        S.r1 = c1 ? i : S.r1;
+    } else if (cand < S.best) {
         S.best = cand;
         S.best_i = i;
     }
 }
 
 // Rows [64 M0 - 2, 64 M0 + 62) clipped to [0, n - 2), then the next phase.
-template <int MB, bool VEC4, int M0>
+template <int MB, bool VEC4, bool HALF, int M0>
 __device__ __forceinline__ void sweep_phase(SweepState<MB, VEC4> &S, const int32_t *__restrict__ D,
-                                            int32_t *bufs, lds_int *lbufs, const uint16_t *tour, int n)
+                                            const uint16_t *__restrict__ H, int32_t *bufs, lds_int *lbufs,
+                                            const uint16_t *tour, int n)
 {
     const int lo = M0 == 0 ? 0 : 64 * M0 - 2;
     const int hi = min(64 * M0 + 62, n - 2);
     for (int i = lo; i < hi; i += 2) {  // lo is even: row parity picks the buffer
-        sweep_row<MB, VEC4, M0, 0>(S, D, bufs, lbufs, tour, n, i);
-        if (i + 1 < hi) sweep_row<MB, VEC4, M0, 1>(S, D, bufs, lbufs, tour, n, i + 1);
+        sweep_row<MB, VEC4, HALF, M0, 0>(S, D, H, bufs, lbufs, tour, n, i);
+        if (i + 1 < hi) sweep_row<MB, VEC4, HALF, M0, 1>(S, D, H, bufs, lbufs, tour, n, i + 1);
     }
     if constexpr (M0 + 1 < MB) {
-        if (hi < n - 2) sweep_phase<MB, VEC4, M0 + 1>(S, D, bufs, lbufs, tour, n);
+        if (hi < n - 2) sweep_phase<MB, VEC4, HALF, M0 + 1>(S, D, H, bufs, lbufs, tour, n);
     }
 }
 
 }  // namespace
 
-template <int MB, bool VEC4>
+template <int MB, bool VEC4, bool HALF>
 __device__ __forceinline__ void twoopt_wave_body(const Inst &I, int p)
 {
     constexpr int ST = WaveCfg<MB, VEC4>::STRIDE, GU = WaveCfg<MB, VEC4>::GUARD;
@@ -364,6 +443,11 @@ __device__ __forceinline__ void twoopt_wave_body(const Inst &I, int p)
     Hdr *h = st.hdr;
     if (h->err || h->done || !h->ee_ran) return;
     const int n = st.n, ns = st.ns, lane = threadIdx.x;
+    const uint16_t *__restrict__ H = st.H;
+    // packed rows: the shift, the window T and the bound 2 (2^s - 1) on |rho|
+    const int shift = HALF ? pack_shift(h->dmax) : 0;
+    const int window = shift == 0 ? 0 : shift == 1 ? 2 : 3;
+    const int64_t rho = 2 * ((int64_t(1) << shift) - 1);
     extern __shared__ __align__(16) unsigned char smem[];
     // [guard][buffer 0][guard][buffer 1][guard], buffer k at GU + k * ST
     int32_t *bufs = reinterpret_cast<int32_t *>(smem) + GU;
@@ -383,15 +467,23 @@ __device__ __forceinline__ void twoopt_wave_body(const Inst &I, int p)
             const int c = lane + 64 * m;
             if (c < n) {
                 const int a = tour[c], b = tour[c + 1 < n ? c + 1 : 0];
-                S.set_off(m, 4 * b);
-                S.ne[m] = -D[size_t(a) * n + b];
+                S.set_off(m, HALF ? 2 * b : 4 * b);
+                S.ne[m] = HALF ? -int(H[size_t(a) * n + b]) : -D[size_t(a) * n + b];
             } else {
                 S.set_off(m, 0);
                 S.ne[m] = kPad;
             }
         }
         // g <- D[x_0][x_c+1]: the first term of row 0, one column to the right
-        if constexpr (kDma && VEC4) {
+        if constexpr (HALF) {
+            wait_lds();
+            dma_half<WaveCfg<MB, VEC4>::RH>(H + size_t(tour[0]) * n, n, lbufs + ST);
+            wait_vmem();
+            compiler_fence();
+#pragma unroll
+            for (int m = 0; m < MB; ++m) S.g[m] = lds_half(bufs + ST, S.off(m));
+            dma_half<WaveCfg<MB, VEC4>::RH>(H + size_t(tour[1]) * n, n, lbufs);
+        } else if constexpr (kDma && VEC4) {
             wait_lds();  // earlier reads of both buffers are done
             dma_row<WaveCfg<MB, VEC4>::RV>(D + size_t(tour[0]) * n, n, lbufs + ST);
             wait_vmem();
@@ -411,27 +503,77 @@ __device__ __forceinline__ void twoopt_wave_body(const Inst &I, int p)
         }
         S.best = kNone;
         S.best_i = 0;
-        sweep_phase<MB, VEC4, 0>(S, D, bufs, lbufs, tour, n);
-        // best (delta, i) of the wave, smallest i on ties
-        const uint64_t key = (uint64_t(uint32_t(S.best) + 0x80000000u) << 32) | uint32_t(S.best_i);
-        const uint64_t win = wave_min_u64(key);
-        const int dbest = int(uint32_t(win >> 32) - 0x80000000u);
-        if (dbest >= 0) break;
-        const int bi = int(uint32_t(win));
-        // smallest j of row bi with delta(bi, j) == dbest
-        const int a0 = tour[bi], a1 = tour[bi + 1];
-        const int e_bi = D[size_t(a0) * n + a1];
-        int bj = n;
-        for (int m = 0; m < MB && bj == n; ++m) {
-            const int c = lane + 64 * m;
-            bool hit = false;
-            if (c >= bi + 2 && c < n && !(bi == 0 && c == n - 1)) {
-                const int xc = tour[c], xn = tour[c + 1 < n ? c + 1 : 0];
-                const int d = D[size_t(a0) * n + xc] + D[size_t(a1) * n + xn] - e_bi - D[size_t(xc) * n + xn];
-                hit = d == dbest;
+        S.v1 = S.v2 = S.v3 = kNone;
+        S.r1 = S.r2 = 0;
+        sweep_phase<MB, VEC4, HALF, 0>(S, D, H, bufs, lbufs, tour, n);
+        int dbest, bi, bj;
+        if constexpr (HALF) {
+            int amin = S.v1;
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) amin = min(amin, __shfl_xor(amin, off, 64));
+            if ((int64_t(amin) << shift) >= rho) break;  // no exchange improves
+            const int lim = amin + window;
+            // exact (delta, i, j) over the rows left in the window
+            uint64_t key = ~0ull;
+            auto exact_row = [&](int r) {
+                const int a0 = tour[r], a1 = tour[r + 1];
+                const int er = D[size_t(a0) * n + a1];
+#pragma unroll
+                for (int m = 0; m < MB; ++m) {
+                    const int c = lane + 64 * m;
+                    if (c >= r + 2 && c < n && !(r == 0 && c == n - 1)) {
+                        const int xc = tour[c], xn = tour[c + 1 < n ? c + 1 : 0];
+                        const int d =
+                            D[size_t(a0) * n + xc] + D[size_t(a1) * n + xn] - er - D[size_t(xc) * n + xn];
+                        const uint64_t k = (uint64_t(uint32_t(d) + 0x80000000u) << 32) | (uint64_t(r) << 16) |
+                                           uint64_t(c);
+                        key = k < key ? k : key;
+                    }
+                }
+            };
+            if (__ballot(S.v3 <= lim)) {
+                for (int r = 0; r + 2 < n; ++r) exact_row(r);
+            } else {
+                uint64_t rows = __ballot(S.v1 <= lim);
+                while (rows) {
+                    const int k = __ffsll((unsigned long long)rows) - 1;
+                    rows &= rows - 1;
+                    exact_row(__builtin_amdgcn_readlane(S.r1, k));
+                }
+                rows = __ballot(S.v2 <= lim);
+                while (rows) {
+                    const int k = __ffsll((unsigned long long)rows) - 1;
+                    rows &= rows - 1;
+                    exact_row(__builtin_amdgcn_readlane(S.r2, k));
+                }
             }
-            const uint64_t bal = __ballot(hit);
-            if (bal) bj = 64 * m + __ffsll((unsigned long long)bal) - 1;
+            const uint64_t win = wave_min_u64(key);
+            dbest = int(uint32_t(win >> 32) - 0x80000000u);
+            if (dbest >= 0) break;
+            bi = int((win >> 16) & 0xffffu);
+            bj = int(win & 0xffffu);
+        } else {
+            // best (delta, i) of the wave, smallest i on ties
+            const uint64_t key = (uint64_t(uint32_t(S.best) + 0x80000000u) << 32) | uint32_t(S.best_i);
+            const uint64_t win = wave_min_u64(key);
+            dbest = int(uint32_t(win >> 32) - 0x80000000u);
+            if (dbest >= 0) break;
+            bi = int(uint32_t(win));
+            // smallest j of row bi with delta(bi, j) == dbest
+            const int a0 = tour[bi], a1 = tour[bi + 1];
+            const int e_bi = D[size_t(a0) * n + a1];
+            bj = n;
+            for (int m = 0; m < MB && bj == n; ++m) {
+                const int c = lane + 64 * m;
+                bool hit = false;
+                if (c >= bi + 2 && c < n && !(bi == 0 && c == n - 1)) {
+                    const int xc = tour[c], xn = tour[c + 1 < n ? c + 1 : 0];
+                    const int d = D[size_t(a0) * n + xc] + D[size_t(a1) * n + xn] - e_bi - D[size_t(xc) * n + xn];
+                    hit = d == dbest;
+                }
+                const uint64_t bal = __ballot(hit);
+                if (bal) bj = 64 * m + __ffsll((unsigned long long)bal) - 1;
+            }
         }
         // reverse tour[bi+1 .. bj]
         const int len = bj - bi;
@@ -457,18 +599,67 @@ __device__ __forceinline__ void twoopt_wave_body(const Inst &I, int p)
     }
 }
 
-template <int MB, bool VEC4>
+template <int MB, bool VEC4, bool HALF>
 __global__ __launch_bounds__(64, DPSO_2OPT_WAVES) void k_2opt_wave(Inst I)
 {
-    twoopt_wave_body<MB, VEC4>(I, int(blockIdx.x));
+    twoopt_wave_body<MB, VEC4, HALF>(I, int(blockIdx.x));
 }
 
-template <int MB, bool VEC4>
+template <int MB, bool VEC4, bool HALF>
 __global__ __launch_bounds__(64, DPSO_2OPT_WAVES) void k_2opt_wave_batch(Batch B)
 {
     int p;
     const Inst &I = batch_pick(B, int(blockIdx.x), p);
-    twoopt_wave_body<MB, VEC4>(I, p);
+    twoopt_wave_body<MB, VEC4, HALF>(I, p);
+}
+
+// Packed rows of one instance: the largest entry of D (into the header,
+// cleared by the run's first launch), then H = D >> shift. Grid-stride over
+// the n^2 entries; blockIdx.y picks the instance of a batch.
+__device__ __forceinline__ void pack_max_body(const Inst &I)
+{
+    __shared__ uint32_t red[4];
+    const size_t nn = size_t(I.st.n) * I.st.n;
+    uint32_t mx = 0;
+    for (size_t k = blockIdx.x * size_t(blockDim.x) + threadIdx.x; k < nn; k += size_t(gridDim.x) * blockDim.x)
+        mx = max(mx, uint32_t(I.D[k]));
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) mx = max(mx, uint32_t(__shfl_xor(int(mx), off, 64)));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < int(blockDim.x >> 6); ++w) mx = max(mx, red[w]);
+        if (mx) atomicMax(&I.st.hdr->dmax, mx);
+    }
+}
+
+__device__ __forceinline__ void pack_rows_body(const Inst &I)
+{
+    const size_t nn = size_t(I.st.n) * I.st.n;
+    const int shift = pack_shift(I.st.hdr->dmax);
+    for (size_t k = blockIdx.x * size_t(blockDim.x) + threadIdx.x; k < nn; k += size_t(gridDim.x) * blockDim.x)
+        I.st.H[k] = uint16_t(uint32_t(I.D[k]) >> shift);
+}
+
+constexpr int kPackThreads = 256;
+
+__global__ __launch_bounds__(kPackThreads) void k_pack_max(Inst I) { pack_max_body(I); }
+__global__ __launch_bounds__(kPackThreads) void k_pack_rows(Inst I) { pack_rows_body(I); }
+__global__ __launch_bounds__(kPackThreads) void k_pack_max_batch(Batch B)
+{
+    Inst I = B.inst[blockIdx.y];
+    I.D = global_ptr(I.D);
+    I.st.hdr = global_ptr(I.st.hdr);
+    I.st.H = global_ptr(I.st.H);
+    pack_max_body(I);
+}
+__global__ __launch_bounds__(kPackThreads) void k_pack_rows_batch(Batch B)
+{
+    Inst I = B.inst[blockIdx.y];
+    I.D = global_ptr(I.D);
+    I.st.hdr = global_ptr(I.st.hdr);
+    I.st.H = global_ptr(I.st.H);
+    pack_rows_body(I);
 }
 
 __global__ __launch_bounds__(kThreads) void k_2opt_rows(Inst I) { twoopt_rows_body(I, int(blockIdx.x)); }
@@ -482,17 +673,17 @@ __global__ __launch_bounds__(kThreads) void k_2opt_rows_batch(Batch B)
 
 namespace {
 
-template <int MB, bool VEC4>
+template <int MB, bool VEC4, bool HALF = false>
 hipError_t launch_wave(const Inst *one, const Batch &B, int grid, int max_ns, hipStream_t s)
 {
     const size_t lds = size_t(WaveCfg<MB, VEC4>::GUARD + 2 * WaveCfg<MB, VEC4>::STRIDE) * 4 + size_t(max_ns) * 2;
-    hipError_t e = allow_lds(k_2opt_wave<MB, VEC4>, lds);
-    if (e == hipSuccess) e = allow_lds(k_2opt_wave_batch<MB, VEC4>, lds);
+    hipError_t e = allow_lds(k_2opt_wave<MB, VEC4, HALF>, lds);
+    if (e == hipSuccess) e = allow_lds(k_2opt_wave_batch<MB, VEC4, HALF>, lds);
     if (e != hipSuccess || grid <= 0) return e;
     if (one)
-        k_2opt_wave<MB, VEC4><<<grid, 64, lds, s>>>(*one);
+        k_2opt_wave<MB, VEC4, HALF><<<grid, 64, lds, s>>>(*one);
     else
-        k_2opt_wave_batch<MB, VEC4><<<grid, 64, lds, s>>>(B);
+        k_2opt_wave_batch<MB, VEC4, HALF><<<grid, 64, lds, s>>>(B);
     return hipGetLastError();
 }
 
@@ -522,10 +713,22 @@ hipError_t launch_class(int cls, const Inst *one, const Batch &B, int grid, int 
     case 7: return launch_wave<4, false>(one, B, grid, max_ns, s);
     case 8: return launch_wave<8, false>(one, B, grid, max_ns, s);
     case 9: return launch_wave<16, false>(one, B, grid, max_ns, s);
-    case 10: return launch_rows(one, B, grid, max_ns, s);
+    case 10: return launch_wave<1, true, true>(one, B, grid, max_ns, s);
+    case 11: return launch_wave<2, true, true>(one, B, grid, max_ns, s);
+    case 12: return launch_wave<4, true, true>(one, B, grid, max_ns, s);
+    case 13: return launch_wave<8, true, true>(one, B, grid, max_ns, s);
+    case 14: return launch_wave<16, true, true>(one, B, grid, max_ns, s);
+    case 15: return launch_rows(one, B, grid, max_ns, s);
     default: return launch_node_swap(one, B, grid, max_ns, s);
     }
 }
+
+constexpr int kFirstHalfClass = 10;
+
+bool half_class(int cls) { return cls >= kFirstHalfClass && cls < kFirstHalfClass + 5; }
+
+// blocks per instance for the packing kernels: ~16 entries per thread
+int pack_blocks(int n) { return int(std::min<int64_t>(1024, (int64_t(n) * n + 4095) / 4096)); }
 
 }  // namespace
 
@@ -533,9 +736,28 @@ int exchange_class(int n, const int32_t *D, int neighbourhood)
 {
     if (neighbourhood == DPSO_NB_NODE_SWAP) return kExchangeClasses - 1;
     if (n > 1024) return kExchangeClasses - 2;
-    const bool vec4 = (n & 3) == 0 && (reinterpret_cast<uintptr_t>(D) & 15) == 0;
     const int mb = n <= 64 ? 0 : n <= 128 ? 1 : n <= 256 ? 2 : n <= 512 ? 3 : 4;
+    if (kHalf && packed_rows(n)) return kFirstHalfClass + mb;
+    const bool vec4 = (n & 3) == 0 && (reinterpret_cast<uintptr_t>(D) & 15) == 0;
     return vec4 ? mb : 5 + mb;
+}
+
+hipError_t launch_2opt_prepare(const Inst &I, hipStream_t s)
+{
+    if (!half_class(exchange_class(I.st.n, I.D, I.kp.ee_neighbourhood))) return hipSuccess;
+    const dim3 grid(pack_blocks(I.st.n), 1);
+    k_pack_max<<<grid, kPackThreads, 0, s>>>(I);
+    k_pack_rows<<<grid, kPackThreads, 0, s>>>(I);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_2opt_prepare(int cls, const Batch &members, int max_n, hipStream_t s)
+{
+    if (!half_class(cls) || members.count <= 0) return hipSuccess;
+    const dim3 grid(pack_blocks(max_n), members.count);
+    k_pack_max_batch<<<grid, kPackThreads, 0, s>>>(members);
+    k_pack_rows_batch<<<grid, kPackThreads, 0, s>>>(members);
+    return hipGetLastError();
 }
 
 hipError_t launch_2opt(const Inst &I, hipStream_t s)

@@ -211,6 +211,43 @@ def test_largest_sizes(dp, n):
     lockstep(dp, D, prm, [1, 3], f"n{n}")
 
 
+def _packed_case_matrix(n, kind, seed):
+    """Symmetric zero-diagonal matrices for the 16-bit row path: `kind` is the
+    largest entry (the shift follows from it) or "ties" (entries 1 and 2) or
+    "ties_wide" (entries 100000 or 200000 plus 0 or 1: shift 2 with ties)."""
+    if kind == "ties":
+        return scenes.random_dist(n, seed=seed, max_mm=3)
+    if kind == "ties_wide":
+        rng = np.random.default_rng(seed)
+        a = 100_000 * rng.integers(1, 3, size=(n, n)) + rng.integers(0, 2, size=(n, n))
+        d = np.triu(a, 1)
+        return np.ascontiguousarray(d + d.T, dtype=np.int32)
+    return scenes.random_dist(n, seed=seed, max_mm=kind)
+
+
+PACKED = [
+    # (name, n, S, gens, matrix, overrides): n a multiple of 8 stages 16-bit
+    # rows; shifts 0, 1, 2, 4 and 12, exchanges tied at the minimum in many
+    # rows (every row then evaluated exactly), each register-block class
+    ("n8_shift4", 8, 9, 6, 1 << 20, dict(ee_trigger=2)),
+    ("n64_shift12_opt", 64, 33, 6, (1 << 28) - 1, dict(ee_trigger=2, ee_max_moves=0)),
+    ("n72_shift1", 72, 20, 6, 100_000, dict(ee_trigger=2)),
+    ("n136_ties_opt", 136, 24, 6, "ties", dict(ee_trigger=2, ee_max_moves=0)),
+    ("n264_ties_shift2", 264, 16, 4, "ties_wide", dict(ee_trigger=2)),
+    ("n520_shift4", 520, 12, 4, 1 << 20, dict(ee_trigger=2)),
+    ("n1016_shift1", 1016, 8, 3, 100_000, dict(ee_trigger=2)),
+    ("n1024_ties", 1024, 8, 2, "ties", dict(ee_trigger=2)),
+    ("n200_shift0_opt", 200, 16, 4, 60_000, dict(ee_trigger=2, ee_max_moves=0)),
+]
+
+
+@pytest.mark.parametrize("name,n,S,gens,kind,kw", PACKED, ids=[c[0] for c in PACKED])
+def test_packed_rows(dp, name, n, S, gens, kind, kw):
+    D = _packed_case_matrix(n, kind, seed=n + 11)
+    prm = scenes.swarm_params(S, gens, seed=29, instance=n, **kw)
+    lockstep(dp, D, prm, sorted({1, 2, gens}), "packed_" + name)
+
+
 NB = scenes.NB_NODE_SWAP
 VARIANTS = [
     # (name, n, S, gens, overrides): node-swap exchange, disturbance mutation,

@@ -71,8 +71,11 @@ def test_state_bytes(dp):
     assert dp.state_bytes(10, 0, 1) == 0
     assert dp.state_bytes(dp.MAX_N + 1, 1, 1) == 0
     a = dp.state_bytes(1000, 4096, 2000)
-    # tours, personal bests and velocities dominate: 2 + 2 + 4 bytes per label
-    assert 4096 * 1024 * 8 <= a < 4096 * 1024 * 8 + (1 << 20)
+    # tours, personal bests and velocities dominate: 2 + 2 + 4 bytes per label;
+    # n = 1000 (a multiple of 8) adds the 16-bit copy of D the exchange stages
+    assert 4096 * 1024 * 8 + 2 * 1000 * 1000 <= a < 4096 * 1024 * 8 + 2 * 1000 * 1000 + (1 << 20)
+    b = dp.state_bytes(1001, 4096, 2000)  # no packed rows
+    assert 4096 * 1024 * 8 <= b < 4096 * 1024 * 8 + (1 << 20)
 
 
 def test_calls_reject_null_pointers_before_device_work(dp):
