@@ -159,11 +159,11 @@ __device__ __forceinline__ void twoopt_rows_body(const Inst &I, int p)
 // exchange with the smallest delta, and every exchange tying with it, has
 // A <= A_min + T, T = floor(4 (2^s - 1) / 2^s) (0, 2 and 3 for s = 0, 1 and
 // s >= 2), and no exchange improves the tour when 2^s A_min >= 2 (2^s - 1).
-// Each lane keeps, over the rows, the two smallest of its row minima of A
-// with their rows and the third smallest value (branch-free updates). At the
-// end, with A_min the wave's minimum, the rows holding a lane minimum <= A_min
-// + T are evaluated exactly from D and the smallest (delta, i, j) is taken
-// over them; should a lane's third value also be in the window, every row is
+// Each lane keeps the three smallest keys 1024 A + i of its row minima (a
+// minimum and two medians of three per row, branch-free). At the end, with
+// A_min the wave's minimum, the rows of the lane keys whose A is <= A_min + T
+// are evaluated exactly from D and the smallest (delta, i, j) is taken over
+// them; should a lane's third key also be in the window, every row is
 // evaluated exactly. The exchange found is the one the int32 sweep finds.
 namespace {
 
@@ -184,6 +184,7 @@ constexpr bool kHalf = DPSO_2OPT_HALF != 0 && kDma;
 
 // s_waitcnt immediates (vmcnt in bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8)
 __device__ inline void wait_vmem() { __builtin_amdgcn_s_waitcnt(0x0F70); }  // vmcnt(0)
+
 __device__ inline void wait_lds() { __builtin_amdgcn_s_waitcnt(0xC07F); }   // lgkmcnt(0)
 
 // LDS-address-space view of the row buffers (taken from the shared array
@@ -218,7 +219,8 @@ __device__ inline void dma_half(const uint16_t *src, int n, lds_int *dst)
     compiler_fence();
 #pragma unroll
     for (int k = 0; k < R; ++k)
-        __builtin_amdgcn_global_load_lds((GV *)(src + 8 * min(lane + 64 * k, q)), (LV *)(dst + 256 * k), 16, 0, 0);
+        __builtin_amdgcn_global_load_lds((GV *)(reinterpret_cast<const char *>(src) + 16 * min(lane + 64 * k, q)),
+                                         (LV *)(dst + 256 * k), 16, 0, 0);
     compiler_fence();
 }
 
@@ -299,9 +301,8 @@ struct SweepState {
     int g[MB];     // gathers of the previous row
     RowPipe<MB, VEC4> pipe[kPrefetch];  // rows in flight (alternating by row parity)
     int best, best_i;
-    // packed rows: the lane's two smallest row minima of A with their rows,
-    // and its third smallest value
-    int v1, r1, v2, r2, v3;
+    // packed rows: the lane's three smallest keys 1024 A + i (k1 <= k2 <= k3)
+    int k1, k2, k3;
 
     __device__ inline int off(int m) const
     {
@@ -331,6 +332,19 @@ __device__ inline int lane_here()
     __asm__ volatile("v_mbcnt_lo_u32_b32 %0, -1, 0\n\tv_mbcnt_hi_u32_b32 %0, -1, %0" : "=v"(v));
     return v;
 }
+
+__device__ inline int med3(int a, int b, int c)
+{
+    int r;
+    __asm__("v_med3_i32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+
+// Key of a row minimum of A: A (capped above; larger values are never in
+// the window) times 1024 plus the row, so keys order by (A, row).
+constexpr int kKeyCap = 1 << 20;
+__device__ inline int row_key(int a, int i) { return min(a, kKeyCap) * 1024 + i; }
+__device__ inline int key_value(int k) { return k >> 10; }
 
 __device__ inline int lds_half(const int32_t *base, int byte_off)
 {
@@ -396,18 +410,24 @@ __device__ __forceinline__ void sweep_row(SweepState<MB, VEC4> &S, const int32_t
         carry = r;
         const int b = HALF ? lds_half(cur, S.off(m)) : lds_word(cur, S.off(m));
         int d = a + b + S.ne[m];
-        if (m == M0) d = (HALF ? lane_here() : lane) + 64 * M0 < i + 2 ? kNone : d;
+        if (m == M0) {
+            if constexpr (HALF) {
+                // lanes below i + 2 - 64 M0 (in [0, 64)) hold columns left of the triangle
+                const uint64_t left = (uint64_t(1) << (i + 2 - 64 * M0)) - 1;
+                d = __builtin_amdgcn_inverse_ballot_w64(left) ? kNone : d;
+            } else {
+                d = lane + 64 * M0 < i + 2 ? kNone : d;
+            }
+        }
         rm = min(rm, d);
         S.g[m] = b;
     }
     const int cand = rm - ei;
     if constexpr (HALF) {
-        const bool c1 = cand < S.v1, c2 = cand < S.v2;
-        S.v3 = c2 ? S.v2 : min(S.v3, cand);
-        S.v2 = c1 ? S.v1 : (c2 ? cand : S.v2);
-        S.r2 = c1 ? S.r1 : (c2 ? i : S.r2);
-        S.v1 = min(S.v1, cand);
-        S.r1 = c1 ? i : S.r1;
+        const int key = row_key(cand, i);
+        S.k3 = med3(S.k2, S.k3, key);
+        S.k2 = med3(S.k1, S.k2, key);
+        S.k1 = min(S.k1, key);
     } else if (cand < S.best) {
         S.best = cand;
         S.best_i = i;
@@ -503,14 +523,14 @@ __device__ __forceinline__ void twoopt_wave_body(const Inst &I, int p)
         }
         S.best = kNone;
         S.best_i = 0;
-        S.v1 = S.v2 = S.v3 = kNone;
-        S.r1 = S.r2 = 0;
+        S.k1 = S.k2 = S.k3 = kNone;
         sweep_phase<MB, VEC4, HALF, 0>(S, D, H, bufs, lbufs, tour, n);
         int dbest, bi, bj;
         if constexpr (HALF) {
-            int amin = S.v1;
+            int kmin = S.k1;
 #pragma unroll
-            for (int off = 32; off >= 1; off >>= 1) amin = min(amin, __shfl_xor(amin, off, 64));
+            for (int off = 32; off >= 1; off >>= 1) kmin = min(kmin, __shfl_xor(kmin, off, 64));
+            const int amin = key_value(kmin);
             if ((int64_t(amin) << shift) >= rho) break;  // no exchange improves
             const int lim = amin + window;
             // exact (delta, i, j) over the rows left in the window
@@ -531,20 +551,20 @@ __device__ __forceinline__ void twoopt_wave_body(const Inst &I, int p)
                     }
                 }
             };
-            if (__ballot(S.v3 <= lim)) {
+            if (__ballot(key_value(S.k3) <= lim)) {
                 for (int r = 0; r + 2 < n; ++r) exact_row(r);
             } else {
-                uint64_t rows = __ballot(S.v1 <= lim);
+                uint64_t rows = __ballot(key_value(S.k1) <= lim);
                 while (rows) {
                     const int k = __ffsll((unsigned long long)rows) - 1;
                     rows &= rows - 1;
-                    exact_row(__builtin_amdgcn_readlane(S.r1, k));
+                    exact_row(__builtin_amdgcn_readlane(S.k1, k) & 1023);
                 }
-                rows = __ballot(S.v2 <= lim);
+                rows = __ballot(key_value(S.k2) <= lim);
                 while (rows) {
                     const int k = __ffsll((unsigned long long)rows) - 1;
                     rows &= rows - 1;
-                    exact_row(__builtin_amdgcn_readlane(S.r2, k));
+                    exact_row(__builtin_amdgcn_readlane(S.k2, k) & 1023);
                 }
             }
             const uint64_t win = wave_min_u64(key);
