@@ -26,9 +26,11 @@ KERNEL_SRC = os.path.join(ROOT, "paper_1706_04399_amd", "csrc", "twoopt.hip")
 
 
 def exchange_kernel_name(n: int) -> str:
+    # <columns per lane / 64, rows start on 16 bytes, 16-bit rows>
     for mb in (1, 2, 4, 8, 16):
         if n <= 64 * mb:
-            return f"k_2opt_wave<{mb}, {'true' if n % 4 == 0 else 'false'}>"
+            packed = n % 8 == 0
+            return f"k_2opt_wave<{mb}, {'true' if n % 4 == 0 else 'false'}, {'true' if packed else 'false'}>"
     return "k_2opt_rows"
 
 
@@ -66,6 +68,8 @@ def measure_ceilings():
     lib.ceil_lds_gather.argtypes = [i32, i32, C.c_void_p, C.c_void_p]
     lib.ceil_lds_write.argtypes = [i32, i32, C.c_void_p, C.c_void_p]
     lib.ceil_lds_dma.argtypes = [C.c_void_p, i32, i32, i32, i32, C.c_void_p, C.c_void_p]
+    lib.ceil_lds_gather16.argtypes = [i32, i32, C.c_void_p, C.c_void_p]
+    lib.ceil_lds_dma16.argtypes = [C.c_void_p, i32, i32, i32, i32, C.c_void_p, C.c_void_p]
     stream = torch.cuda.current_stream()
     sh = C.c_void_p(stream.cuda_stream)
     big = torch.randint(0, 1 << 20, (4 << 20,), dtype=torch.int32, device="cuda")   # 16 MB
@@ -103,10 +107,17 @@ def measure_ceilings():
     t = timed(lambda: lib.ceil_lds_dma(C.c_void_p(mat.data_ptr()), 1000, 1000, waves, reps,
                                        C.c_void_p(sink.data_ptr()), sh))
     lds_dma = waves * (reps + 1) * 4096 / t / 1e9                 # GB/s of 4 KB rows staged
+    t = timed(lambda: lib.ceil_lds_dma16(C.c_void_p(mat.data_ptr()), 1000, 1000, waves, reps,
+                                         C.c_void_p(sink.data_ptr()), sh))
+    lds_dma16 = waves * (reps + 1) * 2048 / t / 1e9               # GB/s of 2 KB rows staged
+    reps = 2000
+    t = timed(lambda: lib.ceil_lds_gather16(blocks, reps, C.c_void_p(sink.data_ptr()), sh))
+    lds_gather16 = blocks * 256 * reps * 16 / t / 1e9             # G reads/s
     torch.cuda.synchronize()
     return {"l2_stream_GBs": round(l2_stream, 1), "l2_random_gather_GBs": round(l2_gather, 1),
             "lds_random_read_G_per_s": round(lds_gather, 1), "lds_row_write_GBs": round(lds_write, 1),
-            "lds_dma_row_GBs": round(lds_dma, 1)}
+            "lds_dma_row_GBs": round(lds_dma, 1), "lds_random_read16_G_per_s": round(lds_gather16, 1),
+            "lds_dma_row16_GBs": round(lds_dma16, 1)}
 
 
 def cpu_baseline(seconds: float):
@@ -473,16 +484,25 @@ def main():
         per_launch = sweeps / launches              # sweeps in one exchange launch
         # time the exchange kernel cannot go below at the measured rates: one
         # random LDS read per exchange, and one staged row per row of the sweep
-        # (n - 1 rows). Rows that go straight from memory into LDS (n a
-        # multiple of 4) stream while the gathers run: the bound is the larger
-        # of the two. Rows staged through registers take LDS store time too.
-        gather_s = per_launch * n * (n - 3) / 2 / (c["lds_random_read_G_per_s"] * 1e9)
+        # (n - 1 rows). Rows that go straight from memory into LDS (16-bit rows
+        # for n a multiple of 8, int32 rows for other multiples of 4) stream
+        # while the gathers run: the bound is the larger of the two (the LDS
+        # serves both, so their sum is given too). Rows staged through
+        # registers take LDS store time as well: the sum.
         mb = next(m for m in (1, 2, 4, 8, 16) if n <= 64 * m)
-        row_bytes = 1024 * ((mb + 3) // 4)          # staged per row (whole 1 KB chunks)
-        if n % 4 == 0:
+        packed = n % 8 == 0 and n <= 1024
+        if packed:
+            gather_s = per_launch * n * (n - 3) / 2 / (c["lds_random_read16_G_per_s"] * 1e9)
+            row_bytes = 1024 * ((mb + 7) // 8)      # staged per row (whole 1 KB chunks)
+            stage_s = per_launch * (n - 1) * row_bytes / (c["lds_dma_row16_GBs"] * 1e9)
+            bound_s = max(gather_s, stage_s)
+        elif n % 4 == 0:
+            gather_s = per_launch * n * (n - 3) / 2 / (c["lds_random_read_G_per_s"] * 1e9)
+            row_bytes = 1024 * ((mb + 3) // 4)
             stage_s = per_launch * (n - 1) * row_bytes / (c["lds_dma_row_GBs"] * 1e9)
             bound_s = max(gather_s, stage_s)
         else:
+            gather_s = per_launch * n * (n - 3) / 2 / (c["lds_random_read_G_per_s"] * 1e9)
             stage_s = per_launch * (n - 2) * 4 * n / (c["lds_row_write_GBs"] * 1e9)
             bound_s = gather_s + stage_s
         c.update({
@@ -491,6 +511,8 @@ def main():
             "exchange_gather_us": round(gather_s * 1e6, 1),
             "exchange_staging_us": round(stage_s * 1e6, 1),
             "exchange_bound_us": round(bound_s * 1e6, 1),
+            "exchange_rows": "16-bit" if packed else "int32",
+            "exchange_lds_sum_us": round((gather_s + stage_s) * 1e6, 1),
             "exchange_measured_us": round(avg_launch_s * 1e6, 1),
             "exchange_frac_of_bound": round(bound_s / avg_launch_s, 4),
             # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, at ~8 integer operations per exchange

@@ -174,7 +174,8 @@ def test_ceiling_benchmarks_load_and_check_arguments():
     """The memory-path micro-benchmarks the benchmark uses for its ceilings:
     exported, and invalid arguments are rejected before any launch."""
     raw = C.CDLL(os.path.join(ROOT, "paper_1706_04399_amd", "libceilings.so"))
-    for name in ("ceil_l2_stream", "ceil_l2_gather", "ceil_lds_gather", "ceil_lds_write", "ceil_lds_dma"):
+    for name in ("ceil_l2_stream", "ceil_l2_gather", "ceil_lds_gather", "ceil_lds_write", "ceil_lds_dma",
+                 "ceil_lds_gather16", "ceil_lds_dma16"):
         assert hasattr(raw, name), name
     vp, i32 = C.c_void_p, C.c_int32
     raw.ceil_l2_stream.argtypes = [vp, C.c_size_t, i32, i32, vp, vp]
@@ -182,6 +183,8 @@ def test_ceiling_benchmarks_load_and_check_arguments():
     raw.ceil_lds_gather.argtypes = [i32, i32, vp, vp]
     raw.ceil_lds_write.argtypes = [i32, i32, vp, vp]
     raw.ceil_lds_dma.argtypes = [vp, i32, i32, i32, i32, vp, vp]
+    raw.ceil_lds_gather16.argtypes = [i32, i32, vp, vp]
+    raw.ceil_lds_dma16.argtypes = [vp, i32, i32, i32, i32, vp, vp]
     fake = vp(256)                     # never dereferenced: rejected first
     assert raw.ceil_l2_stream(None, 1 << 24, 1024, 1, fake, None) != 0
     assert raw.ceil_l2_stream(fake, 1 << 24, 1020, 1, fake, None) != 0   # not a multiple of 8
@@ -191,4 +194,9 @@ def test_ceiling_benchmarks_load_and_check_arguments():
     assert raw.ceil_lds_dma(fake, 1000, 1002, 8, 1, fake, None) != 0     # not a multiple of 4
     assert raw.ceil_lds_dma(fake, 1000, 2048, 8, 1, fake, None) != 0     # longer than a buffer
     assert raw.ceil_lds_dma(None, 1000, 1000, 8, 1, fake, None) != 0
+    assert raw.ceil_lds_gather16(0, 1, fake, None) != 0
+    assert raw.ceil_lds_gather16(8, 1, None, None) != 0
+    assert raw.ceil_lds_dma16(fake, 1000, 1004, 8, 1, fake, None) != 0   # not a multiple of 8
+    assert raw.ceil_lds_dma16(fake, 1000, 2048, 8, 1, fake, None) != 0   # longer than a buffer
+    assert raw.ceil_lds_dma16(None, 1000, 1000, 8, 1, fake, None) != 0
     assert raw.ceil_lds_write(8, 0, fake, None) != 0
