@@ -29,7 +29,7 @@ def exchange_kernel_name(n: int) -> str:
     # <columns per lane / 64, rows start on 16 bytes, 16-bit rows>
     for mb in (1, 2, 4, 8, 16):
         if n <= 64 * mb:
-            packed = n % 8 == 0
+            packed = n % 8 == 0 and n > 256
             return f"k_2opt_wave<{mb}, {'true' if n % 4 == 0 else 'false'}, {'true' if packed else 'false'}>"
     return "k_2opt_rows"
 
@@ -151,11 +151,12 @@ def cpu_baseline(seconds: float):
                       f"generation {gens + 1} on 1 thread, {dt1:.1f} s"}
 
 
-def bench_batch(count: int, generations: int):
+def bench_batch(count: int, generations: int, plain_leg: bool = True):
     """Batched workload: `count` independent instances (n log-uniform in
     [20, 500], facades and bridges by seed), swarm 256 each, edge exchange on
     stall. Solves/s of the batched path (one captured graph per run) against
-    the plain path solving the same instances one at a time."""
+    the plain path solving the same instances one at a time (skipped when
+    plain_leg is false: then only the batched path runs)."""
     import torch
     from paper_1706_04399_amd import dpso, scenes
 
@@ -164,16 +165,18 @@ def bench_batch(count: int, generations: int):
     Ds = [dpso.build_dist(s) for s in sc]
     torch.cuda.synchronize()
     # plain path
-    t0 = time.perf_counter()
-    plain = []
-    for D, p in zip(Ds, prm):
-        st = dpso.init_nn(D, p)
-        dpso.run(D, p, st, generations)
-        plain.append(st)
-    torch.cuda.synchronize()
-    t_plain = time.perf_counter() - t0
-    plain_best = [dpso.get_best(st)[1] for st in plain]
-    del plain
+    t_plain, plain_best = None, None
+    if plain_leg:
+        t0 = time.perf_counter()
+        plain = []
+        for D, p in zip(Ds, prm):
+            st = dpso.init_nn(D, p)
+            dpso.run(D, p, st, generations)
+            plain.append(st)
+        torch.cuda.synchronize()
+        t_plain = time.perf_counter() - t0
+        plain_best = [dpso.get_best(st)[1] for st in plain]
+        del plain
     # batched path
     stream = torch.cuda.Stream()
     b = dpso.Batch(list(zip(Ds, prm)), stream=stream)
@@ -183,12 +186,13 @@ def bench_batch(count: int, generations: int):
     stream.synchronize()
     t_batch = time.perf_counter() - t0
     batch_best = [dpso.get_best(st, stream)[1] for st in b.states]
-    same = plain_best == batch_best
+    same = plain_best == batch_best if plain_leg else None
     ns = [s.n for s in sc]
     return {
         "metric": "batched solves/s", "value": round(count / t_batch, 3), "unit": "solves/s",
-        "plain_value": round(count / t_plain, 3), "speedup_vs_plain": round(t_plain / t_batch, 3),
-        "seconds_batched": round(t_batch, 3), "seconds_plain": round(t_plain, 3),
+        "plain_value": round(count / t_plain, 3) if plain_leg else None,
+        "speedup_vs_plain": round(t_plain / t_batch, 3) if plain_leg else None,
+        "seconds_batched": round(t_batch, 3), "seconds_plain": round(t_plain, 3) if plain_leg else None,
         "particle_iters_per_s": round(256 * generations * count / t_batch, 1),
         "identical_results": same, "n_gpus": 1, "higher_is_better": True, "dtype": "int32",
         "data": "synthetic",
@@ -383,6 +387,8 @@ def main():
     ap.add_argument("--batch", type=int, default=0,
                     help="run the batched workload with this many instances instead")
     ap.add_argument("--batch-generations", type=int, default=500)
+    ap.add_argument("--no-plain", action="store_true",
+                    help="with --batch: time only the batched path, not the one-at-a-time path")
     ap.add_argument("--serve", type=int, default=0,
                     help="serve this many re-planning requests instead")
     ap.add_argument("--rate", type=float, default=50.0)
@@ -401,7 +407,7 @@ def main():
         sys.exit(2)
 
     if args.batch:
-        print(json.dumps(bench_batch(args.batch, args.batch_generations)), flush=True)
+        print(json.dumps(bench_batch(args.batch, args.batch_generations, not args.no_plain)), flush=True)
         return
     if args.ablation:
         print(json.dumps(bench_ablation(args.ablation, args.ablation_generations)), flush=True)
@@ -485,12 +491,12 @@ def main():
         # time the exchange kernel cannot go below at the measured rates: one
         # random LDS read per exchange, and one staged row per row of the sweep
         # (n - 1 rows). Rows that go straight from memory into LDS (16-bit rows
-        # for n a multiple of 8, int32 rows for other multiples of 4) stream
+        # for n a multiple of 8 above 256, int32 rows for other multiples of 4) stream
         # while the gathers run: the bound is the larger of the two (the LDS
         # serves both, so their sum is given too). Rows staged through
         # registers take LDS store time as well: the sum.
         mb = next(m for m in (1, 2, 4, 8, 16) if n <= 64 * m)
-        packed = n % 8 == 0 and n <= 1024
+        packed = n % 8 == 0 and 256 < n <= 1024
         if packed:
             gather_s = per_launch * n * (n - 3) / 2 / (c["lds_random_read16_G_per_s"] * 1e9)
             row_bytes = 1024 * ((mb + 7) // 8)      # staged per row (whole 1 KB chunks)

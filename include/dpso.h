@@ -148,7 +148,7 @@ dpso_status dpso_validate_params(const dpso_params *params, int32_t n);
  * swarm_size and max_generations generations; 0 if the sizes are out of
  * range. The buffer holds every particle's tour, personal best and
  * velocity, costs, the global best, the cost trace and the scratch space
- * used by the generation loop, and, for n a multiple of 8 up to 1024, the
+ * used by the generation loop, and, for n a multiple of 8 in (256, 1024], the
  * 16-bit copy of D (2 n^2 bytes) that the edge exchange stages, rewritten by
  * every run: dpso_run allocates nothing. */
 size_t dpso_state_bytes(int32_t n, int32_t swarm_size, int32_t max_generations);

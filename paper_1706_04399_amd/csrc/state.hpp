@@ -15,7 +15,7 @@
 //   flags  int32  [S]      mutation scratch: duplicate marks
 //   keep   int32  [S]      mutation scratch: kept marks
 //   H      uint16 [n][n]   D >> shift, the rows the edge exchange stages when
-//                          n is a multiple of 8 and at most 1024 (else empty);
+//                          n is a multiple of 8 in (256, 1024] (else empty);
 //                          rewritten by every run
 #pragma once
 
@@ -45,8 +45,9 @@ struct Hdr {
 };
 
 // The edge exchange stages 16-bit rows (H = D >> shift) for these n: rows of
-// 2n bytes then start on 16 bytes, and a sweep fits one wavefront.
-inline bool packed_rows(int32_t n) { return n >= 8 && n <= 1024 && (n & 7) == 0; }
+// 2n bytes then start on 16 bytes, a sweep fits one wavefront, and a row
+// takes fewer 1 KB load chunks than an int32 row (at n <= 256 both take one).
+inline bool packed_rows(int32_t n) { return n > 256 && n <= 1024 && (n & 7) == 0; }
 
 // shift that brings the largest entry of D under 2^16
 __host__ __device__ inline int pack_shift(uint32_t dmax)

@@ -145,7 +145,8 @@ __device__ __forceinline__ void twoopt_rows_body(const Inst &I, int p)
 #ifndef DPSO_2OPT_DMA
 #define DPSO_2OPT_DMA 1
 #endif
-// Rows staged as 16-bit values (see below) when n is a multiple of 8.
+// Rows staged as 16-bit values (see below) when n is a multiple of 8 above
+// 256 (at n <= 256 an int32 row is one 1 KB load chunk already).
 #ifndef DPSO_2OPT_HALF
 #define DPSO_2OPT_HALF 1
 #endif
@@ -733,19 +734,16 @@ hipError_t launch_class(int cls, const Inst *one, const Batch &B, int grid, int 
     case 7: return launch_wave<4, false>(one, B, grid, max_ns, s);
     case 8: return launch_wave<8, false>(one, B, grid, max_ns, s);
     case 9: return launch_wave<16, false>(one, B, grid, max_ns, s);
-    case 10: return launch_wave<1, true, true>(one, B, grid, max_ns, s);
-    case 11: return launch_wave<2, true, true>(one, B, grid, max_ns, s);
-    case 12: return launch_wave<4, true, true>(one, B, grid, max_ns, s);
-    case 13: return launch_wave<8, true, true>(one, B, grid, max_ns, s);
-    case 14: return launch_wave<16, true, true>(one, B, grid, max_ns, s);
-    case 15: return launch_rows(one, B, grid, max_ns, s);
+    case 10: return launch_wave<8, true, true>(one, B, grid, max_ns, s);
+    case 11: return launch_wave<16, true, true>(one, B, grid, max_ns, s);
+    case 12: return launch_rows(one, B, grid, max_ns, s);
     default: return launch_node_swap(one, B, grid, max_ns, s);
     }
 }
 
-constexpr int kFirstHalfClass = 10;
+constexpr int kFirstHalfClass = 10;  // 16-bit rows at 8 and 16 columns per lane (n in (256, 1024])
 
-bool half_class(int cls) { return cls >= kFirstHalfClass && cls < kFirstHalfClass + 5; }
+bool half_class(int cls) { return cls >= kFirstHalfClass && cls < kFirstHalfClass + 2; }
 
 // blocks per instance for the packing kernels: ~16 entries per thread
 int pack_blocks(int n) { return int(std::min<int64_t>(1024, (int64_t(n) * n + 4095) / 4096)); }
@@ -757,7 +755,7 @@ int exchange_class(int n, const int32_t *D, int neighbourhood)
     if (neighbourhood == DPSO_NB_NODE_SWAP) return kExchangeClasses - 1;
     if (n > 1024) return kExchangeClasses - 2;
     const int mb = n <= 64 ? 0 : n <= 128 ? 1 : n <= 256 ? 2 : n <= 512 ? 3 : 4;
-    if (kHalf && packed_rows(n)) return kFirstHalfClass + mb;
+    if (kHalf && packed_rows(n)) return kFirstHalfClass + (mb - 3);  // mb is 3 or 4 here
     const bool vec4 = (n & 3) == 0 && (reinterpret_cast<uintptr_t>(D) & 15) == 0;
     return vec4 ? mb : 5 + mb;
 }

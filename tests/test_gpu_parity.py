@@ -226,18 +226,19 @@ def _packed_case_matrix(n, kind, seed):
 
 
 PACKED = [
-    # (name, n, S, gens, matrix, overrides): n a multiple of 8 stages 16-bit
-    # rows; shifts 0, 1, 2, 4 and 12, exchanges tied at the minimum in many
-    # rows (every row then evaluated exactly), each register-block class
-    ("n8_shift4", 8, 9, 6, 1 << 20, dict(ee_trigger=2)),
-    ("n64_shift12_opt", 64, 33, 6, (1 << 28) - 1, dict(ee_trigger=2, ee_max_moves=0)),
-    ("n72_shift1", 72, 20, 6, 100_000, dict(ee_trigger=2)),
-    ("n136_ties_opt", 136, 24, 6, "ties", dict(ee_trigger=2, ee_max_moves=0)),
+    # (name, n, S, gens, matrix, overrides): n a multiple of 8 in (256, 1024]
+    # stages 16-bit rows; shifts 0, 1, 2, 4 and 12, exchanges tied at the
+    # minimum in many rows (every row then evaluated exactly), both register-
+    # block classes and their edges
+    ("n264_shift4", 264, 16, 4, 1 << 20, dict(ee_trigger=2)),
+    ("n320_shift12_opt", 320, 8, 3, (1 << 28) - 1, dict(ee_trigger=2, ee_max_moves=0)),
+    ("n264_ties_opt", 264, 8, 3, "ties", dict(ee_trigger=2, ee_max_moves=0)),
     ("n264_ties_shift2", 264, 16, 4, "ties_wide", dict(ee_trigger=2)),
+    ("n512_shift1", 512, 12, 4, 100_000, dict(ee_trigger=2)),
     ("n520_shift4", 520, 12, 4, 1 << 20, dict(ee_trigger=2)),
     ("n1016_shift1", 1016, 8, 3, 100_000, dict(ee_trigger=2)),
     ("n1024_ties", 1024, 8, 2, "ties", dict(ee_trigger=2)),
-    ("n200_shift0_opt", 200, 16, 4, 60_000, dict(ee_trigger=2, ee_max_moves=0)),
+    ("n400_shift0_opt", 400, 8, 3, 60_000, dict(ee_trigger=2, ee_max_moves=0)),
 ]
 
 
