@@ -214,12 +214,22 @@ def test_largest_sizes(dp, n):
 def _packed_case_matrix(n, kind, seed):
     """Symmetric zero-diagonal matrices for the 16-bit row path: `kind` is the
     largest entry (the shift follows from it) or "ties" (entries 1 and 2) or
-    "ties_wide" (entries 100000 or 200000 plus 0 or 1: shift 2 with ties)."""
+    "ties_wide" (entries 100000 or 200000 plus 0 or 1: shift 2 with ties) or
+    "lowbit" / "lowbit2" (shift 1 / 2, near-ties decided by the dropped bits)."""
     if kind == "ties":
         return scenes.random_dist(n, seed=seed, max_mm=3)
     if kind == "ties_wide":
         rng = np.random.default_rng(seed)
         a = 100_000 * rng.integers(1, 3, size=(n, n)) + rng.integers(0, 2, size=(n, n))
+        d = np.triu(a, 1)
+        return np.ascontiguousarray(d + d.T, dtype=np.int32)
+    if kind in ("lowbit", "lowbit2"):
+        # shift 1 (or 2): sums of H tie often and the dropped low bits decide
+        rng = np.random.default_rng(seed)
+        if kind == "lowbit":
+            a = 65_536 + 2 * rng.integers(0, 4, size=(n, n)) + rng.integers(0, 2, size=(n, n))
+        else:
+            a = 131_072 + 4 * rng.integers(0, 3, size=(n, n)) + rng.integers(0, 4, size=(n, n))
         d = np.triu(a, 1)
         return np.ascontiguousarray(d + d.T, dtype=np.int32)
     return scenes.random_dist(n, seed=seed, max_mm=kind)
@@ -239,6 +249,9 @@ PACKED = [
     ("n1016_shift1", 1016, 8, 3, 100_000, dict(ee_trigger=2)),
     ("n1024_ties", 1024, 8, 2, "ties", dict(ee_trigger=2)),
     ("n400_shift0_opt", 400, 8, 3, 60_000, dict(ee_trigger=2, ee_max_moves=0)),
+    ("n264_lowbit", 264, 16, 4, "lowbit", dict(ee_trigger=2)),
+    ("n288_lowbit2_opt", 288, 8, 3, "lowbit2", dict(ee_trigger=2, ee_max_moves=0)),
+    ("n1000_lowbit", 1000, 8, 2, "lowbit", dict(ee_trigger=2)),
 ]
 
 
