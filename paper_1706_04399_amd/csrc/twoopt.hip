@@ -325,21 +325,8 @@ __device__ inline int lds_word(const int32_t *base, int byte_off)
     return *reinterpret_cast<const int32_t *>(reinterpret_cast<const char *>(base) + byte_off);
 }
 
-// Lane index computed in place: a volatile asm is neither hoisted nor
-// merged, so no register has to hold it across the sweep.
-__device__ inline int lane_here()
-{
-    int v;
-    __asm__ volatile("v_mbcnt_lo_u32_b32 %0, -1, 0\n\tv_mbcnt_hi_u32_b32 %0, -1, %0" : "=v"(v));
-    return v;
-}
-
-__device__ inline int med3(int a, int b, int c)
-{
-    int r;
-    __asm__("v_med3_i32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
-    return r;
-}
+// median of three (one v_med3_i32)
+__device__ inline int med3(int a, int b, int c) { return max(min(a, b), min(max(a, b), c)); }
 
 // Key of a row minimum of A: A (capped above; larger values are never in
 // the window) times 1024 plus the row, so keys order by (A, row).
