@@ -29,7 +29,7 @@ def exchange_kernel_name(n: int) -> str:
     # <columns per lane / 64, rows start on 16 bytes, 16-bit rows>
     for mb in (1, 2, 4, 8, 16):
         if n <= 64 * mb:
-            packed = n % 8 == 0 and n > 256
+            packed = 8 <= n and (n > 256 or n % 4 != 0)
             return f"k_2opt_wave<{mb}, {'true' if n % 4 == 0 else 'false'}, {'true' if packed else 'false'}>"
     return "k_2opt_rows"
 
@@ -491,12 +491,12 @@ def main():
         # time the exchange kernel cannot go below at the measured rates: one
         # random LDS read per exchange, and one staged row per row of the sweep
         # (n - 1 rows). Rows that go straight from memory into LDS (16-bit rows
-        # for n a multiple of 8 above 256, int32 rows for other multiples of 4) stream
+        # for n above 256 or not a multiple of 4, int32 rows otherwise) stream
         # while the gathers run: the bound is the larger of the two (the LDS
         # serves both, so their sum is given too). Rows staged through
         # registers take LDS store time as well: the sum.
         mb = next(m for m in (1, 2, 4, 8, 16) if n <= 64 * m)
-        packed = n % 8 == 0 and 256 < n <= 1024
+        packed = 8 <= n <= 1024 and (n > 256 or n % 4 != 0)
         if packed:
             gather_s = per_launch * n * (n - 3) / 2 / (c["lds_random_read16_G_per_s"] * 1e9)
             row_bytes = 1024 * ((mb + 7) // 8)      # staged per row (whole 1 KB chunks)

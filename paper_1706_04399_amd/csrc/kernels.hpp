@@ -29,7 +29,7 @@ hipError_t launch_batch_end(const Batch &items, const Batch &instances, int tota
 // twoopt.hip: the edge-exchange kernel depends on the neighbourhood, on n
 // (columns held per lane) and on the alignment of D; instances of one class
 // share a launch. The last class is the node-swap neighbourhood.
-constexpr int kExchangeClasses = 14;
+constexpr int kExchangeClasses = 17;
 int exchange_class(int n, const int32_t *D, int neighbourhood);
 hipError_t launch_2opt(const Inst &I, hipStream_t s);
 hipError_t launch_batch_2opt(int cls, const Batch &items, int total, int max_ns, hipStream_t s);

@@ -14,9 +14,9 @@
 //   trace  int64  [cap]     global-best cost after each generation
 //   flags  int32  [S]      mutation scratch: duplicate marks
 //   keep   int32  [S]      mutation scratch: kept marks
-//   H      uint16 [n][n]   D >> shift, the rows the edge exchange stages when
-//                          n is a multiple of 8 in (256, 1024] (else empty);
-//                          rewritten by every run
+//   H      uint16 [n][hs]  D >> shift with rows padded to hs = n rounded up to
+//                          8 (zeros), the rows the edge exchange stages when
+//                          packed_rows(n) (else empty); rewritten by every run
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -44,10 +44,17 @@ struct Hdr {
     int32_t pad;
 };
 
-// The edge exchange stages 16-bit rows (H = D >> shift) for these n: rows of
-// 2n bytes then start on 16 bytes, a sweep fits one wavefront, and a row
-// takes fewer 1 KB load chunks than an int32 row (at n <= 256 both take one).
-inline bool packed_rows(int32_t n) { return n > 256 && n <= 1024 && (n & 7) == 0; }
+// The edge exchange stages 16-bit rows (H = D >> shift, padded rows of
+// 2 hs bytes that start on 16 bytes) for these n: a sweep fits one
+// wavefront, and either a row takes fewer 1 KB load chunks than an int32 row
+// (n > 256) or int32 rows of D do not start on 16 bytes (n not a multiple of
+// 4) and would have to pass through registers. At n <= 256, n a multiple of
+// 4, int32 rows of D go straight into LDS in one chunk already.
+__host__ __device__ inline bool packed_rows(int32_t n)
+{
+    return n >= 8 && n <= 1024 && (n > 256 || (n & 3) != 0);
+}
+__host__ __device__ inline int32_t packed_stride(int32_t n) { return (n + 7) & ~7; }
 
 // shift that brings the largest entry of D under 2^16
 __host__ __device__ inline int pack_shift(uint32_t dmax)
@@ -82,7 +89,7 @@ inline Layout make_layout(int32_t n, int32_t S, int32_t cap)
     L.trace = take(size_t(cap) * 8);
     L.flags = take(size_t(S) * 4);
     L.keep = take(size_t(S) * 4);
-    L.H = take(packed_rows(n) ? size_t(n) * n * 2 : 0);
+    L.H = take(packed_rows(n) ? size_t(n) * packed_stride(n) * 2 : 0);
     L.total = o;
     return L;
 }

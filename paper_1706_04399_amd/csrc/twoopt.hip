@@ -145,15 +145,17 @@ __device__ __forceinline__ void twoopt_rows_body(const Inst &I, int p)
 #ifndef DPSO_2OPT_DMA
 #define DPSO_2OPT_DMA 1
 #endif
-// Rows staged as 16-bit values (see below) when n is a multiple of 8 above
-// 256 (at n <= 256 an int32 row is one 1 KB load chunk already).
+// Rows staged as 16-bit values (see below) for the n of packed_rows(): all
+// n in [8, 1024] except multiples of 4 up to 256, whose int32 rows go
+// straight into LDS in one 1 KB load chunk already.
 #ifndef DPSO_2OPT_HALF
 #define DPSO_2OPT_HALF 1
 #endif
 
 // Packed rows. The sweep is bound by staging rows into LDS, 4n bytes each.
 // With H = D >> s, s the smallest shift that brings every entry of D under
-// 2^16 (0 while distances stay below 65.536 m), a row takes 2n bytes. Writing
+// 2^16 (0 while distances stay below 65.536 m), a row takes 2n bytes (padded
+// to a multiple of 16 bytes, so rows of every n go straight into LDS). Writing
 // each entry as D = 2^s h + r (h its entry of H, 0 <= r < 2^s), the sum
 //   A(i, j) = H[x_i][x_j] + H[x_i+1][x_j+1] - H[x_i][x_i+1] - H[x_j][x_j+1]
 // gives delta(i, j) = 2^s A(i, j) + rho with |rho| <= 2 (2^s - 1). So the
@@ -209,14 +211,15 @@ __device__ inline void dma_row(const int32_t *src, int n, lds_int *dst)
     compiler_fence();
 }
 
-// A row of n uint16 (n a multiple of 8) into an LDS buffer: chunk k of
-// 64 x 16 bytes lands at byte 1024 k of dst, chunk indices clamped to the row.
+// A padded row of hs uint16 (hs a multiple of 8) into an LDS buffer: chunk k
+// of 64 x 16 bytes lands at byte 1024 k of dst, chunk indices clamped to the
+// row.
 template <int R>
-__device__ inline void dma_half(const uint16_t *src, int n, lds_int *dst)
+__device__ inline void dma_half(const uint16_t *src, int hs, lds_int *dst)
 {
     typedef __attribute__((address_space(1))) const void GV;
     typedef __attribute__((address_space(3))) void LV;
-    const int lane = threadIdx.x, q = (n >> 3) - 1;
+    const int lane = threadIdx.x, q = (hs >> 3) - 1;
     compiler_fence();
 #pragma unroll
     for (int k = 0; k < R; ++k)
@@ -364,7 +367,8 @@ __device__ __forceinline__ void sweep_row(SweepState<MB, VEC4> &S, const int32_t
         wait_vmem();
         wait_lds();
         compiler_fence();
-        if (i + 4 <= n) dma_half<WaveCfg<MB, VEC4>::RH>(H + size_t(label) * n, n, lbufs + (1 - BI) * ST);
+        const int hs = packed_stride(n);
+        if (i + 4 <= n) dma_half<WaveCfg<MB, VEC4>::RH>(H + size_t(label) * hs, hs, lbufs + (1 - BI) * ST);
     } else if constexpr (kDma && VEC4) {
         // e_i = D[x_i][x_i+1] and the label x_i+2 come from the registers of
         // the lanes owning columns i and i + 1 (in this phase, blocks M0 - 1
@@ -452,6 +456,7 @@ __device__ __forceinline__ void twoopt_wave_body(const Inst &I, int p)
     if (h->err || h->done || !h->ee_ran) return;
     const int n = st.n, ns = st.ns, lane = threadIdx.x;
     const uint16_t *__restrict__ H = st.H;
+    const int hs = packed_stride(n);  // row stride of H
     // packed rows: the shift, the window T and the bound 2 (2^s - 1) on |rho|
     const int shift = HALF ? pack_shift(h->dmax) : 0;
     const int window = shift == 0 ? 0 : shift == 1 ? 2 : 3;
@@ -476,7 +481,7 @@ __device__ __forceinline__ void twoopt_wave_body(const Inst &I, int p)
             if (c < n) {
                 const int a = tour[c], b = tour[c + 1 < n ? c + 1 : 0];
                 S.set_off(m, HALF ? 2 * b : 4 * b);
-                S.ne[m] = HALF ? -int(H[size_t(a) * n + b]) : -D[size_t(a) * n + b];
+                S.ne[m] = HALF ? -int(H[size_t(a) * hs + b]) : -D[size_t(a) * n + b];
             } else {
                 S.set_off(m, 0);
                 S.ne[m] = kPad;
@@ -485,12 +490,12 @@ __device__ __forceinline__ void twoopt_wave_body(const Inst &I, int p)
         // g <- D[x_0][x_c+1]: the first term of row 0, one column to the right
         if constexpr (HALF) {
             wait_lds();
-            dma_half<WaveCfg<MB, VEC4>::RH>(H + size_t(tour[0]) * n, n, lbufs + ST);
+            dma_half<WaveCfg<MB, VEC4>::RH>(H + size_t(tour[0]) * hs, hs, lbufs + ST);
             wait_vmem();
             compiler_fence();
 #pragma unroll
             for (int m = 0; m < MB; ++m) S.g[m] = lds_half(bufs + ST, S.off(m));
-            dma_half<WaveCfg<MB, VEC4>::RH>(H + size_t(tour[1]) * n, n, lbufs);
+            dma_half<WaveCfg<MB, VEC4>::RH>(H + size_t(tour[1]) * hs, hs, lbufs);
         } else if constexpr (kDma && VEC4) {
             wait_lds();  // earlier reads of both buffers are done
             dma_row<WaveCfg<MB, VEC4>::RV>(D + size_t(tour[0]) * n, n, lbufs + ST);
@@ -643,10 +648,13 @@ __device__ __forceinline__ void pack_max_body(const Inst &I)
 
 __device__ __forceinline__ void pack_rows_body(const Inst &I)
 {
-    const size_t nn = size_t(I.st.n) * I.st.n;
+    const int n = I.st.n, hs = packed_stride(n);
+    const size_t total = size_t(n) * hs;
     const int shift = pack_shift(I.st.hdr->dmax);
-    for (size_t k = blockIdx.x * size_t(blockDim.x) + threadIdx.x; k < nn; k += size_t(gridDim.x) * blockDim.x)
-        I.st.H[k] = uint16_t(uint32_t(I.D[k]) >> shift);
+    for (size_t k = blockIdx.x * size_t(blockDim.x) + threadIdx.x; k < total; k += size_t(gridDim.x) * blockDim.x) {
+        const int r = int(k / hs), c = int(k - size_t(r) * hs);
+        I.st.H[k] = c < n ? uint16_t(uint32_t(I.D[size_t(r) * n + c]) >> shift) : uint16_t(0);
+    }
 }
 
 constexpr int kPackThreads = 256;
@@ -721,19 +729,22 @@ hipError_t launch_class(int cls, const Inst *one, const Batch &B, int grid, int 
     case 7: return launch_wave<4, false>(one, B, grid, max_ns, s);
     case 8: return launch_wave<8, false>(one, B, grid, max_ns, s);
     case 9: return launch_wave<16, false>(one, B, grid, max_ns, s);
-    case 10: return launch_wave<8, true, true>(one, B, grid, max_ns, s);
-    case 11: return launch_wave<16, true, true>(one, B, grid, max_ns, s);
-    case 12: return launch_rows(one, B, grid, max_ns, s);
+    case 10: return launch_wave<1, true, true>(one, B, grid, max_ns, s);
+    case 11: return launch_wave<2, true, true>(one, B, grid, max_ns, s);
+    case 12: return launch_wave<4, true, true>(one, B, grid, max_ns, s);
+    case 13: return launch_wave<8, true, true>(one, B, grid, max_ns, s);
+    case 14: return launch_wave<16, true, true>(one, B, grid, max_ns, s);
+    case 15: return launch_rows(one, B, grid, max_ns, s);
     default: return launch_node_swap(one, B, grid, max_ns, s);
     }
 }
 
-constexpr int kFirstHalfClass = 10;  // 16-bit rows at 8 and 16 columns per lane (n in (256, 1024])
+constexpr int kFirstHalfClass = 10;  // 16-bit rows at 1, 2, 4, 8, 16 columns per lane
 
-bool half_class(int cls) { return cls >= kFirstHalfClass && cls < kFirstHalfClass + 2; }
+bool half_class(int cls) { return cls >= kFirstHalfClass && cls < kFirstHalfClass + 5; }
 
 // blocks per instance for the packing kernels: ~16 entries per thread
-int pack_blocks(int n) { return int(std::min<int64_t>(1024, (int64_t(n) * n + 4095) / 4096)); }
+int pack_blocks(int n) { return int(std::min<int64_t>(1024, (int64_t(n) * packed_stride(n) + 4095) / 4096)); }
 
 }  // namespace
 
@@ -742,7 +753,7 @@ int exchange_class(int n, const int32_t *D, int neighbourhood)
     if (neighbourhood == DPSO_NB_NODE_SWAP) return kExchangeClasses - 1;
     if (n > 1024) return kExchangeClasses - 2;
     const int mb = n <= 64 ? 0 : n <= 128 ? 1 : n <= 256 ? 2 : n <= 512 ? 3 : 4;
-    if (kHalf && packed_rows(n)) return kFirstHalfClass + (mb - 3);  // mb is 3 or 4 here
+    if (kHalf && packed_rows(n)) return kFirstHalfClass + mb;
     const bool vec4 = (n & 3) == 0 && (reinterpret_cast<uintptr_t>(D) & 15) == 0;
     return vec4 ? mb : 5 + mb;
 }

@@ -236,10 +236,10 @@ def _packed_case_matrix(n, kind, seed):
 
 
 PACKED = [
-    # (name, n, S, gens, matrix, overrides): n a multiple of 8 in (256, 1024]
-    # stages 16-bit rows; shifts 0, 1, 2, 4 and 12, exchanges tied at the
-    # minimum in many rows (every row then evaluated exactly), both register-
-    # block classes and their edges
+    # (name, n, S, gens, matrix, overrides): n above 256 or not a multiple of 4
+    # stages 16-bit rows (padded to 8 entries); shifts 0, 1, 2, 4 and 12,
+    # exchanges tied at the minimum in many rows (every row then evaluated
+    # exactly), every register-block class, padded and unpadded rows
     ("n264_shift4", 264, 16, 4, 1 << 20, dict(ee_trigger=2)),
     ("n320_shift12_opt", 320, 8, 3, (1 << 28) - 1, dict(ee_trigger=2, ee_max_moves=0)),
     ("n264_ties_opt", 264, 8, 3, "ties", dict(ee_trigger=2, ee_max_moves=0)),
@@ -252,6 +252,14 @@ PACKED = [
     ("n264_lowbit", 264, 16, 4, "lowbit", dict(ee_trigger=2)),
     ("n288_lowbit2_opt", 288, 8, 3, "lowbit2", dict(ee_trigger=2, ee_max_moves=0)),
     ("n1000_lowbit", 1000, 8, 2, "lowbit", dict(ee_trigger=2)),
+    ("n9_pad_shift1", 9, 7, 6, 100_000, dict(ee_trigger=2, ee_max_moves=0)),
+    ("n63_pad_ties_opt", 63, 16, 4, "ties", dict(ee_trigger=2, ee_max_moves=0)),
+    ("n101_pad_lowbit", 101, 16, 4, "lowbit", dict(ee_trigger=2)),
+    ("n250_pad_shift4", 250, 12, 4, 1 << 20, dict(ee_trigger=2)),
+    ("n263_pad_lowbit2_opt", 263, 8, 3, "lowbit2", dict(ee_trigger=2, ee_max_moves=0)),
+    ("n260_pad4_shift1", 260, 12, 4, 100_000, dict(ee_trigger=2)),
+    ("n517_pad_ties", 517, 8, 3, "ties", dict(ee_trigger=2)),
+    ("n1021_pad_shift12", 1021, 8, 2, (1 << 28) - 1, dict(ee_trigger=2)),
 ]
 
 

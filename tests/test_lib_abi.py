@@ -72,10 +72,14 @@ def test_state_bytes(dp):
     assert dp.state_bytes(dp.MAX_N + 1, 1, 1) == 0
     a = dp.state_bytes(1000, 4096, 2000)
     # tours, personal bests and velocities dominate: 2 + 2 + 4 bytes per label;
-    # n = 1000 (a multiple of 8) adds the 16-bit copy of D the exchange stages
+    # n = 1000 adds the 16-bit copy of D the exchange stages (rows padded to 8)
     assert 4096 * 1024 * 8 + 2 * 1000 * 1000 <= a < 4096 * 1024 * 8 + 2 * 1000 * 1000 + (1 << 20)
-    b = dp.state_bytes(1001, 4096, 2000)  # no packed rows
-    assert 4096 * 1024 * 8 <= b < 4096 * 1024 * 8 + (1 << 20)
+    b = dp.state_bytes(1001, 4096, 2000)
+    assert 4096 * 1024 * 8 + 2 * 1001 * 1008 <= b < 4096 * 1024 * 8 + 2 * 1001 * 1008 + (1 << 20)
+    c = dp.state_bytes(256, 64, 10)   # int32 rows of D staged directly: no copy
+    assert c < 64 * 256 * 8 + (1 << 16)
+    d = dp.state_bytes(255, 64, 10)   # rows of D not on 16 bytes: a padded 16-bit copy
+    assert d >= 255 * 256 * 2
 
 
 def test_calls_reject_null_pointers_before_device_work(dp):
