@@ -148,9 +148,10 @@ dpso_status dpso_validate_params(const dpso_params *params, int32_t n);
  * swarm_size and max_generations generations; 0 if the sizes are out of
  * range. The buffer holds every particle's tour, personal best and
  * velocity, costs, the global best, the cost trace and the scratch space
- * used by the generation loop, and, for n a multiple of 8 in (256, 1024], the
- * 16-bit copy of D (2 n^2 bytes) that the edge exchange stages, rewritten by
- * every run: dpso_run allocates nothing. */
+ * used by the generation loop, and, for 8 <= n <= 1024 except multiples of 4
+ * up to 256, the 16-bit copy of D with rows padded to a multiple of 8 entries
+ * (2 n ceil8(n) bytes) that the edge exchange stages, rewritten by every run:
+ * dpso_run allocates nothing. */
 size_t dpso_state_bytes(int32_t n, int32_t swarm_size, int32_t max_generations);
 
 /* A planar surface to inspect (Sect. 2.1): an axis-aligned rectangle in the
