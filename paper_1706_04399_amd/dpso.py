@@ -141,9 +141,17 @@ def _check(status: int):
 
 
 def _stream(stream):
+    """The HIP stream a call enqueues on. A torch stream other than the
+    current one first waits for the work already queued on the current stream
+    (torch's pool streams do not synchronise with it), so tensors the caller
+    just wrote there, such as an uploaded distance matrix, are complete
+    before the library reads them. A raw handle is used as given."""
     if stream is None:
         return C.c_void_p(torch.cuda.current_stream().cuda_stream)
     if isinstance(stream, torch.cuda.Stream):
+        cur = torch.cuda.current_stream(stream.device)
+        if cur.cuda_stream != stream.cuda_stream:
+            stream.wait_stream(cur)
         return C.c_void_p(stream.cuda_stream)
     return C.c_void_p(int(stream))
 
