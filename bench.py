@@ -56,9 +56,10 @@ def measure_ceilings():
     ``libceilings.so``), each timed with events on the stream it runs on:
     16-byte reads streamed from L2 (a 16 MB buffer of which each XCD reads its
     own 2 MB), random 4-byte reads over a 4 MB buffer (a distance matrix at
-    n = 1000), random 4-byte LDS reads within a 4 KB row per wave, and 16-byte
-    LDS writes of 4 KB rows. Occupancy of the LDS tests matches the
-    edge-exchange kernel (16 waves per CU)."""
+    n = 1000), random 4-byte LDS reads within a 4 KB row per wave and random
+    2-byte reads within a 2 KB row, 16-byte LDS writes of 4 KB rows, and rows
+    loaded straight into LDS (4 KB int32 rows, 2 KB 16-bit rows). Occupancy of
+    the LDS tests matches the edge-exchange kernel (16 waves per CU)."""
     import ctypes as C
     import torch
     lib = C.CDLL(os.path.join(ROOT, "paper_1706_04399_amd", "libceilings.so"))
