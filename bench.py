@@ -26,11 +26,13 @@ KERNEL_SRC = os.path.join(ROOT, "paper_1706_04399_amd", "csrc", "twoopt.hip")
 
 
 def exchange_kernel_name(n: int) -> str:
-    # <columns per lane / 64, rows start on 16 bytes, 16-bit rows>
+    # <columns per lane / 64, rows go straight into LDS, 16-bit rows>; 16-bit
+    # rows are padded to 16 bytes, so they always go straight into LDS
     for mb in (1, 2, 4, 8, 16):
         if n <= 64 * mb:
             packed = 8 <= n and (n > 256 or n % 4 != 0)
-            return f"k_2opt_wave<{mb}, {'true' if n % 4 == 0 else 'false'}, {'true' if packed else 'false'}>"
+            direct = packed or n % 4 == 0
+            return f"k_2opt_wave<{mb}, {'true' if direct else 'false'}, {'true' if packed else 'false'}>"
     return "k_2opt_rows"
 
 

@@ -1,0 +1,34 @@
+"""Host-side behaviour of the benchmark script (no GPU): the one-GPU
+contract and the name of the exchange kernel a workload runs."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode == 2
+    assert "one GPU" in r.stdout + r.stderr
+
+
+@pytest.mark.parametrize("n,name", [
+    (1000, "k_2opt_wave<16, true, true>"),    # 16-bit rows (n > 256)
+    (1024, "k_2opt_wave<16, true, true>"),
+    (1021, "k_2opt_wave<16, true, true>"),    # padded 16-bit rows
+    (260, "k_2opt_wave<8, true, true>"),
+    (256, "k_2opt_wave<4, true, false>"),     # int32 rows straight into LDS
+    (255, "k_2opt_wave<4, true, true>"),      # rows of D off 16 bytes: 16-bit copy
+    (64, "k_2opt_wave<1, true, false>"),
+    (9, "k_2opt_wave<1, true, true>"),
+    (5, "k_2opt_wave<1, false, false>"),      # below 8: int32 rows through registers
+    (1025, "k_2opt_rows"),
+])
+def test_exchange_kernel_name_follows_the_row_policy(n, name):
+    assert bench.exchange_kernel_name(n) == name
