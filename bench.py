@@ -154,12 +154,38 @@ def cpu_baseline(seconds: float):
                       f"generation {gens + 1} on 1 thread, {dt1:.1f} s"}
 
 
-def bench_batch(count: int, generations: int, plain_leg: bool = True):
+def batch_cpu_baseline(sc, prm, generations: int, seconds: float, gpu_best):
+    """The oracle solving the batch's instances one after another (the first
+    ones, until about `seconds` of solving), distance builds excluded as on
+    the GPU side; also whether each best cost equals the batched result."""
+    import ctypes as C
+    import oracle
+    gomp = C.CDLL("libgomp.so.1")               # the OpenMP runtime the oracle runs on
+    threads = int(gomp.omp_get_max_threads())
+    done, same, t_solve = 0, True, 0.0
+    for i, (s, p) in enumerate(zip(sc, prm)):
+        D = oracle.build_dist(s)
+        t0 = time.perf_counter()
+        st = oracle.new_state(D, p)
+        oracle.run(D, p, st, generations)
+        t_solve += time.perf_counter() - t0
+        done += 1
+        same = same and int(st.FG) == int(gpu_best[i])
+        if t_solve >= seconds:
+            break
+    return {"value": round(done / t_solve, 3), "unit": "solves/s", "cores": threads, "kind": "oracle",
+            "sample": f"instances 0-{done - 1} of the same batch, one after another on {threads} "
+                      f"threads, {t_solve:.1f} s of solving (distance builds excluded)",
+            "identical_best_costs": same}
+
+
+def bench_batch(count: int, generations: int, plain_leg: bool = True, cpu_seconds: float = 0.0):
     """Batched workload: `count` independent instances (n log-uniform in
     [20, 500], facades and bridges by seed), swarm 256 each, edge exchange on
     stall. Solves/s of the batched path (one captured graph per run) against
     the plain path solving the same instances one at a time (skipped when
-    plain_leg is false: then only the batched path runs)."""
+    plain_leg is false: then only the batched path runs), and the oracle on
+    the host for about cpu_seconds (0: skipped)."""
     import torch
     from paper_1706_04399_amd import dpso, scenes
 
@@ -191,6 +217,7 @@ def bench_batch(count: int, generations: int, plain_leg: bool = True):
     batch_best = [dpso.get_best(st, stream)[1] for st in b.states]
     same = plain_best == batch_best if plain_leg else None
     ns = [s.n for s in sc]
+    cpu = batch_cpu_baseline(sc, prm, generations, cpu_seconds, batch_best) if cpu_seconds > 0 else None
     return {
         "metric": "batched solves/s", "value": round(count / t_batch, 3), "unit": "solves/s",
         "plain_value": round(count / t_plain, 3) if plain_leg else None,
@@ -203,6 +230,7 @@ def bench_batch(count: int, generations: int, plain_leg: bool = True):
                                f"max {max(ns)}), facade/bridge by seed, swarm 256, "
                                f"{generations} generations, edge exchange on stall",
                    "instances": count, "generations": generations},
+        "cpu_baseline": cpu,
     }
 
 
@@ -410,7 +438,8 @@ def main():
         sys.exit(2)
 
     if args.batch:
-        print(json.dumps(bench_batch(args.batch, args.batch_generations, not args.no_plain)), flush=True)
+        print(json.dumps(bench_batch(args.batch, args.batch_generations, not args.no_plain,
+                                     0.0 if args.no_cpu else args.cpu_seconds)), flush=True)
         return
     if args.ablation:
         print(json.dumps(bench_ablation(args.ablation, args.ablation_generations)), flush=True)
