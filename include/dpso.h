@@ -259,7 +259,10 @@ dpso_status dpso_init_nn(const int32_t *d_dist, int32_t n, const dpso_params *pa
  * the state holds, so run(a) followed by run(b) equals run(a + b). params
  * must be those given to dpso_init_nn. Enqueues only; a state that was not
  * initialised for (n, swarm_size) is reported as DPSO_E_STATE by the next
- * dpso_get_info / dpso_get_best. */
+ * dpso_get_info / dpso_get_best. When the edge exchange is on and it stages
+ * 16-bit rows (see dpso_state_bytes), the run first rewrites the state's
+ * copy of D (two small kernels), so D may change between runs; D must meet
+ * the contract that dpso_check_dist checks. */
 dpso_status dpso_run(const int32_t *d_dist, int32_t n, const dpso_params *params, void *d_state,
                      size_t state_bytes, int32_t generations, void *stream);
 
