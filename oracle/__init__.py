@@ -55,7 +55,9 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        _lib = C.CDLL(build())
+        # DPSO_ORACLE_LIB names another build of this source (the tests load
+        # copies with planted mistakes through it to show the pins fail)
+        _lib = C.CDLL(os.environ.get("DPSO_ORACLE_LIB") or build())
         P = C.c_void_p
         i32, i64, u32, u64 = C.c_int32, C.c_int64, C.c_uint32, C.c_uint64
         sig = {
