@@ -155,12 +155,11 @@ class GpuExecutor:
     """Runs an admitted batch with the batched C ABI; keeps distance matrices
     of recent scenes resident on the device (a bounded cache)."""
 
-    def __init__(self, batched: bool = True, stream=None, cache_scenes: int = 64):
+    def __init__(self, stream=None, cache_scenes: int = 64):
         import torch
         from . import dpso
         self.dpso, self.torch = dpso, torch
-        self.batched = batched
-        self.stream = stream if stream is not None else (torch.cuda.Stream() if batched else None)
+        self.stream = stream if stream is not None else torch.cuda.Stream()
         self.cache = collections.OrderedDict()
         self.cache_scenes = cache_scenes
 
@@ -184,14 +183,7 @@ class GpuExecutor:
     def solve(self, batch):
         d = self.dpso
         Ds = [self._dist(r) for r in batch]
-        if self.batched:
-            b = d.Batch([(D, r.params) for D, r in zip(Ds, batch)], stream=self.stream)
-            # each swarm stops at its own max_generations
-            b.init().run(max(r.params["max_generations"] for r in batch))
-            return [d.get_best(st, self.stream)[1] for st in b.states]
-        out = []
-        for D, r in zip(Ds, batch):
-            st = d.init_nn(D, r.params, stream=self.stream)
-            d.run(D, r.params, st, r.params["max_generations"], stream=self.stream)
-            out.append(d.get_best(st, self.stream)[1])
-        return out
+        b = d.Batch([(D, r.params) for D, r in zip(Ds, batch)], stream=self.stream)
+        # each swarm stops at its own max_generations
+        b.init().run(max(r.params["max_generations"] for r in batch))
+        return [d.get_best(st, self.stream)[1] for st in b.states]

@@ -501,7 +501,7 @@ def test_served_results_equal_single_solves(dp):
     from paper_1706_04399_amd import serve
     reqs = serve.poisson_requests(12, rate=400.0, seed=9, n_lo=20, n_hi=120, swarm=32,
                                   generations=15)
-    ex = serve.GpuExecutor(batched=True)
+    ex = serve.GpuExecutor()
     budget = 3 * max(ex.footprint(r) for r in reqs)
     recs = serve.serve(reqs, ex, serve.Scheduler(budget, ex.footprint))
     assert sorted(r.rid for r in recs) == list(range(12))
