@@ -5,6 +5,7 @@ matrices and synthetic swarm states are produced on the oracle side and fed
 to both implementations. Nothing computed by the library is ever fed to the
 oracle.
 """
+import hashlib
 import sys
 
 import numpy as np
@@ -88,3 +89,55 @@ def synthetic_state(D: np.ndarray, prm: dict, t: int, seed: int, max_vlen=None) 
     st.done = 0
     st.trace[: t + 1] = st.FG
     return st
+
+
+# ---------------------------------------------------------------- digests
+# A whole swarm state reduced to a few hashes, so that the oracle's state at
+# the end of a full-length run can be stored as a small fixture and compared
+# field by field with the library's exported state. Labels hash as int32,
+# costs as int64, a velocity as the concatenation of every particle's
+# transposition list (its first vlen pairs).
+
+def _h(a, dtype) -> str:
+    return hashlib.sha256(np.ascontiguousarray(a, dtype=dtype).tobytes()).hexdigest()[:16]
+
+
+def _velocity_words(V, vlen) -> np.ndarray:
+    parts = [np.asarray(V[p, : int(vlen[p])], dtype=np.int64).reshape(-1) for p in range(len(vlen))]
+    return np.concatenate(parts) if parts else np.zeros(0, np.int64)
+
+
+def digest(*, X, P, F, FP, vlen, V, G, trace, best_cost, generation, stall, done, sweeps, moves,
+           reshuffled, full=False) -> dict:
+    d = {"best_cost": int(best_cost), "generation": int(generation), "stall": int(stall),
+         "done": int(done), "sweeps": int(sweeps), "moves": int(moves), "reshuffled": int(reshuffled),
+         "h_G": _h(G, np.int32), "h_trace": _h(trace, np.int64), "h_X": _h(X, np.int32),
+         "h_P": _h(P, np.int32), "h_F": _h(F, np.int64), "h_FP": _h(FP, np.int64),
+         "h_vlen": _h(vlen, np.int32), "h_V": _h(_velocity_words(V, vlen), np.int32)}
+    if full:
+        d["G"] = [int(v) for v in G]
+        d["trace"] = [int(v) for v in trace]
+    return d
+
+
+def oracle_digest(st: "oracle.State", full=False) -> dict:
+    return digest(X=st.X, P=st.P, F=st.F, FP=st.FP, vlen=st.VL, V=st.V, G=st.G,
+                  trace=st.trace[: st.t + 1], best_cost=st.FG, generation=st.t, stall=st.stall,
+                  done=st.done, sweeps=st.n_sweeps, moves=st.n_moves, reshuffled=st.n_reshuffled,
+                  full=full)
+
+
+def library_digest(dp, state, n: int, S: int, stream=None, full=False) -> dict:
+    """The same digest of a library state (exported through the C ABI)."""
+    ex = dp.export_state(state, n, S, stream)
+    info = dp.get_info(state, stream)
+    return digest(X=ex["X"], P=ex["P"], F=ex["F"], FP=ex["FP"], vlen=ex["vlen"], V=ex["V"],
+                  G=ex["G"], trace=ex["trace"], best_cost=ex["best_cost"],
+                  generation=ex["generation"], stall=ex["stall"], done=ex["done"],
+                  sweeps=info["sweeps"], moves=info["moves"], reshuffled=info["reshuffled"],
+                  full=full)
+
+
+def digest_mismatches(got: dict, want: dict) -> list:
+    return [f"{k}: library {got.get(k)!r:.60} oracle {want[k]!r:.60}"
+            for k in want if k in got and got[k] != want[k]]
