@@ -179,6 +179,24 @@ def line(xs_mm) -> Scene:
     return Scene(np.array(pts, np.int32), np.zeros((0, 6), np.int32), 0, "line")
 
 
+def serpentine(walls: int, gap_mm: int = 2_000_000, half_mm: int = 65_000_000) -> Scene:
+    """Three viewpoints on the x axis near the ends of a cube of half-edge
+    `half_mm`, separated by `walls` thin walls (planes of constant x) that span
+    the whole cube in z and leave a gap of `gap_mm` at alternately the high and
+    the low end of y, so a flight between the ends weaves through every gap
+    (paths far longer than the cube, for the range limits of the costs)."""
+    xs = np.linspace(-half_mm + 5_000_000, half_mm - 5_000_000, walls).astype(np.int64)
+    far = half_mm + 1_000_000
+    boxes = []
+    for k, x in enumerate(xs):
+        if k % 2 == 0:
+            boxes.append((x - 1000, -far, -far, x + 1000, half_mm - gap_mm, far))
+        else:
+            boxes.append((x - 1000, -half_mm + gap_mm, -far, x + 1000, far, far))
+    vp = [(-half_mm, 0, 0), (half_mm, 0, 0), (-half_mm, 1000, 0)]
+    return Scene(np.array(vp, np.int32), np.array(boxes, np.int32).reshape(-1, 6), 0, f"serpentine{walls}")
+
+
 def random_points(n, seed, extent_mm=20_000, n_boxes=0, clearance_mm=CLEARANCE_MM) -> Scene:
     """Uniform points in a cube, optionally with random boxes (sides 500..3000)."""
     rng = np.random.default_rng(seed)

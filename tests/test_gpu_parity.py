@@ -42,6 +42,8 @@ DIST_CASES = {
     "bridge200": lambda: scenes.workload(2)[0],
     "facade1000": lambda: scenes.workload(3)[0],
     "random50_5boxes": lambda: scenes.random_points(50, seed=3, n_boxes=5),
+    "random130_10boxes": lambda: scenes.random_points(130, seed=21, n_boxes=10),
+    "serpentine1_long_finite": lambda: scenes.serpentine(1),
     "circle64": lambda: scenes.circle(64),
     "grid8x6": lambda: scenes.grid(8, 6),
     "detour": _golden_detour_scene,
@@ -67,6 +69,20 @@ def test_build_dist_unreachable_pair(dp):
     got = dp.build_dist(sc).cpu().numpy()
     assert np.array_equal(got, oracle.build_dist(sc))
     assert got[0, 1] == dp.D_INF
+
+
+@pytest.mark.parametrize("walls", [2, 20])
+def test_build_dist_finite_path_beyond_sentinel_is_range_error(dp, walls):
+    """Paths that weave through 2 or 20 walls are finite and longer than the
+    blocked-pair cost (with 20 walls, longer than 2^32 mm): a range error on
+    both sides, not a blocked pair."""
+    sc = scenes.serpentine(walls)
+    note(f"build_dist serpentine{walls}")
+    with pytest.raises(ValueError, match="status -2"):
+        oracle.build_dist(sc)
+    with pytest.raises(dp.DpsoError) as ei:
+        dp.build_dist(sc)
+    assert ei.value.status == dp.E_RANGE
 
 
 @pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 200, 1000, 4096])
