@@ -243,6 +243,23 @@ size_t dpso_dist_work_bytes(int32_t n, int32_t n_boxes);
 dpso_status dpso_build_dist(const dpso_scene *scene, int32_t *d_dist, void *d_work,
                             size_t work_bytes, void *stream);
 
+/* Largest workspace of dpso_build_dist_noalloc (32 MiB): enough for visibility
+ * graphs of up to 2880 nodes (n + 8 * n_boxes). */
+#define DPSO_NOALLOC_WORK_BYTES 33554432
+
+/* dpso_build_dist without a workspace argument, for callers that cannot
+ * allocate device memory (serving loops, harnesses that forbid allocation).
+ * The same kernels and result as dpso_build_dist; the workspace is a static
+ * device buffer of DPSO_NOALLOC_WORK_BYTES that the library holds on every
+ * device it runs on until the process ends. Calls nothing that allocates.
+ * Returns DPSO_E_NOMEM if dpso_dist_work_bytes(n, n_boxes) exceeds
+ * DPSO_NOALLOC_WORK_BYTES (checked before any device work); the other
+ * errors as dpso_build_dist. Calls on one device share that buffer: calls
+ * that overlap in time on one device (other host threads, other streams)
+ * race and must be serialised by the caller. Synchronises `stream`, so it
+ * cannot be captured into a graph. */
+dpso_status dpso_build_dist_noalloc(const dpso_scene *scene, int32_t *d_dist, void *stream);
+
 /* Initial swarm (pseudo code of Sect. 3.3, deterministic initialisation of
  * Sect. 3.2.1): the first ceil(S * det_permille / 1000) particles start from
  * nearest-neighbour tours whose start labels are spread evenly over 0..n-1

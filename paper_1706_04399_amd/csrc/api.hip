@@ -397,6 +397,70 @@ dpso_status run_impl(const int32_t *d_dist, int32_t n, const dpso_params *params
     return ok();
 }
 
+// Scene checks shared by both distance-builder entry points (before any
+// device work, so they run without a GPU).
+dpso_status check_scene(const dpso_scene *scene, const int32_t *d_dist)
+{
+    if (!scene || !d_dist) return fail(DPSO_E_INVAL, "scene and d_dist must be non-NULL");
+    const int32_t n = scene->n, nb = scene->n_boxes;
+    if (n < 1) return fail(DPSO_E_INVAL, "scene has n = %d viewpoints", n);
+    if (n > DPSO_MAX_N) return fail(DPSO_E_RANGE, "n = %d exceeds DPSO_MAX_N", n);
+    if (nb < 0 || (nb > 0 && !scene->boxes_mm) || !scene->vp_mm)
+        return fail(DPSO_E_INVAL, "bad box list (n_boxes = %d)", nb);
+    if (int64_t(n) + 8 * int64_t(nb) > DPSO_MAX_GRAPH)
+        return fail(DPSO_E_RANGE, "n + 8 * n_boxes = %lld exceeds DPSO_MAX_GRAPH = %d",
+                    (long long)(int64_t(n) + 8 * int64_t(nb)), DPSO_MAX_GRAPH);
+    if (scene->clearance_mm < 0) return fail(DPSO_E_INVAL, "clearance must be >= 0");
+    const int64_t lim = int64_t(1) << 26;
+    for (int64_t i = 0; i < 3 * int64_t(n); ++i)
+        if (scene->vp_mm[i] <= -lim || scene->vp_mm[i] >= lim)
+            return fail(DPSO_E_RANGE, "viewpoint coordinate %d outside (-2^26, 2^26)", scene->vp_mm[i]);
+    for (int32_t b = 0; b < nb; ++b)
+        for (int a = 0; a < 3; ++a) {
+            const int64_t lo = scene->boxes_mm[6 * b + a], hi = scene->boxes_mm[6 * b + 3 + a];
+            if (lo > hi) return fail(DPSO_E_INVAL, "box %d has lo > hi on axis %d", b, a);
+            if (lo - scene->clearance_mm <= -lim || hi + scene->clearance_mm >= lim)
+                return fail(DPSO_E_RANGE, "inflated box %d outside (-2^26, 2^26)", b);
+        }
+    return DPSO_OK;
+}
+
+dpso_status build_dist_on(const dpso_scene *scene, int32_t *d_dist, void *work, hipStream_t s)
+{
+    int range_error = 0;
+    HIP_TRY(dpso::build_dist(scene->vp_mm, scene->n, scene->boxes_mm, scene->n_boxes, scene->clearance_mm,
+                             d_dist, work, s, &range_error),
+            "build_dist");
+    if (range_error) return fail(DPSO_E_RANGE, "a finite path cost reaches DPSO_D_INF");
+    return ok();
+}
+
+// Workspace of dpso_build_dist_noalloc: one static buffer per device, held
+// until the process ends. Its device address is looked up once per device
+// (with that device current); host code uses only that address, never the
+// array's own name, which on the host is a stand-in and not device memory.
+__device__ __align__(256) unsigned char dist_scratch[DPSO_NOALLOC_WORK_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+dpso_status noalloc_scratch(void **out)
+{
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev), "current device");
+    if (dev < 0 || dev >= kMaxDevices) return fail(DPSO_E_DEVICE, "device %d outside 0..%d", dev, kMaxDevices - 1);
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(dist_scratch)), "address of the static workspace");
+        if (!p) return fail(DPSO_E_DEVICE, "static workspace has no device address");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return DPSO_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -429,36 +493,25 @@ size_t dpso_dist_work_bytes(int32_t n, int32_t n_boxes)
 dpso_status dpso_build_dist(const dpso_scene *scene, int32_t *d_dist, void *d_work, size_t work_bytes,
                             void *stream)
 {
-    if (!scene || !d_dist || !d_work) return fail(DPSO_E_INVAL, "scene, d_dist and d_work must be non-NULL");
-    const int32_t n = scene->n, nb = scene->n_boxes;
-    if (n < 1) return fail(DPSO_E_INVAL, "scene has n = %d viewpoints", n);
-    if (n > DPSO_MAX_N) return fail(DPSO_E_RANGE, "n = %d exceeds DPSO_MAX_N", n);
-    if (nb < 0 || (nb > 0 && !scene->boxes_mm) || !scene->vp_mm)
-        return fail(DPSO_E_INVAL, "bad box list (n_boxes = %d)", nb);
-    if (int64_t(n) + 8 * int64_t(nb) > DPSO_MAX_GRAPH)
-        return fail(DPSO_E_RANGE, "n + 8 * n_boxes = %lld exceeds DPSO_MAX_GRAPH = %d",
-                    (long long)(int64_t(n) + 8 * int64_t(nb)), DPSO_MAX_GRAPH);
-    if (scene->clearance_mm < 0) return fail(DPSO_E_INVAL, "clearance must be >= 0");
-    const int64_t lim = int64_t(1) << 26;
-    for (int64_t i = 0; i < 3 * int64_t(n); ++i)
-        if (scene->vp_mm[i] <= -lim || scene->vp_mm[i] >= lim)
-            return fail(DPSO_E_RANGE, "viewpoint coordinate %d outside (-2^26, 2^26)", scene->vp_mm[i]);
-    for (int32_t b = 0; b < nb; ++b)
-        for (int a = 0; a < 3; ++a) {
-            const int64_t lo = scene->boxes_mm[6 * b + a], hi = scene->boxes_mm[6 * b + 3 + a];
-            if (lo > hi) return fail(DPSO_E_INVAL, "box %d has lo > hi on axis %d", b, a);
-            if (lo - scene->clearance_mm <= -lim || hi + scene->clearance_mm >= lim)
-                return fail(DPSO_E_RANGE, "inflated box %d outside (-2^26, 2^26)", b);
-        }
-    if (work_bytes < dpso::dist_work_bytes(n, nb))
-        return fail(DPSO_E_NOMEM, "workspace of %zu bytes, %zu needed", work_bytes,
-                    dpso::dist_work_bytes(n, nb));
-    int range_error = 0;
-    HIP_TRY(dpso::build_dist(scene->vp_mm, n, scene->boxes_mm, nb, scene->clearance_mm, d_dist, d_work,
-                             as_stream(stream), &range_error),
-            "build_dist");
-    if (range_error) return fail(DPSO_E_RANGE, "a finite path cost reaches DPSO_D_INF");
-    return ok();
+    if (!d_work) return fail(DPSO_E_INVAL, "d_work must be non-NULL");
+    dpso_status st = check_scene(scene, d_dist);
+    if (st) return st;
+    const size_t need = dpso::dist_work_bytes(scene->n, scene->n_boxes);
+    if (work_bytes < need) return fail(DPSO_E_NOMEM, "workspace of %zu bytes, %zu needed", work_bytes, need);
+    return build_dist_on(scene, d_dist, d_work, as_stream(stream));
+}
+
+dpso_status dpso_build_dist_noalloc(const dpso_scene *scene, int32_t *d_dist, void *stream)
+{
+    dpso_status st = check_scene(scene, d_dist);
+    if (st) return st;
+    const size_t need = dpso::dist_work_bytes(scene->n, scene->n_boxes);
+    if (need > DPSO_NOALLOC_WORK_BYTES)
+        return fail(DPSO_E_NOMEM, "scene needs %zu bytes of workspace, more than the %d of the static buffer",
+                    need, DPSO_NOALLOC_WORK_BYTES);
+    void *work = nullptr;
+    if ((st = noalloc_scratch(&work))) return st;
+    return build_dist_on(scene, d_dist, work, as_stream(stream));
 }
 
 dpso_status dpso_init_nn(const int32_t *d_dist, int32_t n, const dpso_params *params, void *d_state,

@@ -17,6 +17,7 @@ _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libdpso.so
 
 OK, E_INVAL, E_RANGE, E_NOMEM, E_DEVICE, E_STATE = 0, -1, -2, -3, -4, -5
 D_INF = (1 << 28) - 1
+NOALLOC_WORK_BYTES = 32 << 20   # static workspace of dpso_build_dist_noalloc
 MAX_N = 4096
 MAX_SWARM = 65536
 EE_OFF, EE_ON_STALL, EE_ALWAYS = 0, 1, 2
@@ -89,6 +90,7 @@ EXPORTS = {
     "dpso_validate_params": (C.c_int32, [C.c_void_p, C.c_int32]),
     "dpso_state_bytes": (C.c_size_t, [C.c_int32, C.c_int32, C.c_int32]),
     "dpso_dist_work_bytes": (C.c_size_t, [C.c_int32, C.c_int32]),
+    "dpso_build_dist_noalloc": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "dpso_build_dist": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
     "dpso_init_nn": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_size_t,
                                  C.c_void_p]),
@@ -198,6 +200,19 @@ def build_dist(scene, out: torch.Tensor | None = None, stream=None, device=None)
     sc = Scene(vp.ctypes.data, n, bx.ctypes.data if nb else None, nb, int(scene.clearance_mm))
     _check(lib().dpso_build_dist(C.byref(sc), _dev(out, torch.int32), C.c_void_p(work.data_ptr()),
                                  work.numel(), _stream(stream)))
+    return out
+
+
+def build_dist_noalloc(scene, out: torch.Tensor | None = None, stream=None, device=None) -> torch.Tensor:
+    """As build_dist, through the entry point whose workspace is the library's
+    static device buffer (no workspace tensor is allocated)."""
+    vp = np.ascontiguousarray(scene.vp_mm, dtype=np.int32)
+    bx = np.ascontiguousarray(scene.boxes_mm, dtype=np.int32)
+    n, nb = vp.shape[0], bx.shape[0]
+    if out is None:
+        out = torch.empty((n, n), dtype=torch.int32, device=device if device is not None else "cuda")
+    sc = Scene(vp.ctypes.data, n, bx.ctypes.data if nb else None, nb, int(scene.clearance_mm))
+    _check(lib().dpso_build_dist_noalloc(C.byref(sc), _dev(out, torch.int32), _stream(stream)))
     return out
 
 

@@ -112,6 +112,28 @@ def test_build_dist_validation(dp):
     assert L.dpso_build_dist(C.byref(sc), fake, fake, 16, None) == dp.E_NOMEM
 
 
+def test_build_dist_noalloc_validation(dp):
+    """The entry point without a workspace checks the scene as dpso_build_dist
+    does, and refuses a scene whose workspace exceeds its static buffer, all
+    before any device work."""
+    import numpy as np
+    L = dp.lib()
+    fake = C.c_void_p(0x1000)
+    assert L.dpso_build_dist_noalloc(None, fake, None) == dp.E_INVAL
+    vp = np.array([[0, 0, 0], [1 << 26, 0, 0]], np.int32)
+    sc = dp.Scene(vp.ctypes.data, 2, None, 0, 0)
+    assert L.dpso_build_dist_noalloc(C.byref(sc), fake, None) == dp.E_RANGE
+    # 2000 viewpoints and 120 boxes: 2960 graph nodes, a 2960^2 x 4 byte matrix
+    vp = np.zeros((2000, 3), np.int32)
+    vp[:, 0] = np.arange(2000) * 10
+    box = np.tile(np.array([[0, 5000, 0, 10, 5010, 10]], np.int32), (120, 1))
+    sc = dp.Scene(vp.ctypes.data, 2000, box.ctypes.data, 120, 0)
+    assert L.dpso_dist_work_bytes(2000, 120) > dp.NOALLOC_WORK_BYTES
+    assert L.dpso_build_dist_noalloc(C.byref(sc), fake, None) == dp.E_NOMEM
+    assert "static buffer" in L.dpso_last_error().decode()
+    assert L.dpso_dist_work_bytes(1000, 20) <= dp.NOALLOC_WORK_BYTES
+
+
 def test_voxel_planner_validation(dp):
     """Host checks of the voxel planner: bad arguments give a zero workspace
     size and an error before any device work."""
