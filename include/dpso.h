@@ -47,6 +47,8 @@ typedef int32_t dpso_status;
 #define DPSO_E_NOMEM (-3)  /* a caller buffer is smaller than required         */
 #define DPSO_E_DEVICE (-4) /* a HIP call failed (text in dpso_last_error)       */
 #define DPSO_E_STATE (-5)  /* state buffer not initialised for this n / swarm  */
+#define DPSO_E_ADMIT (-6)  /* a served request needs more device memory than the
+                              whole serving budget (dpso_request_footprint)    */
 
 #define DPSO_D_INF 268435455 /* 2^28 - 1 */
 #define DPSO_MAX_N 4096      /* largest number of viewpoints                    */
@@ -153,6 +155,16 @@ dpso_status dpso_validate_params(const dpso_params *params, int32_t n);
  * (2 n ceil8(n) bytes) that the edge exchange stages, rewritten by every run:
  * dpso_run allocates nothing. */
 size_t dpso_state_bytes(int32_t n, int32_t swarm_size, int32_t max_generations);
+
+/* Device bytes a served plan request holds while it stays resident (the
+ * re-planning of criterion (iv) of Sect. 1 keeps the distance matrix and the
+ * swarm on the device between requests): its swarm state
+ * (dpso_state_bytes(n, swarm_size, max_generations)) and its int32 [n][n]
+ * distance matrix, built with dpso_build_dist_noalloc, which needs no
+ * workspace of its own. Writes *bytes (may be NULL). Returns DPSO_E_ADMIT if
+ * they exceed `budget` (such a request can never be admitted), DPSO_E_INVAL
+ * or DPSO_E_RANGE for parameters dpso_validate_params rejects. Host only. */
+dpso_status dpso_request_footprint(int32_t n, const dpso_params *params, size_t budget, size_t *bytes);
 
 /* A planar surface to inspect (Sect. 2.1): an axis-aligned rectangle in the
  * plane {coordinate normal_axis = lo_mm[normal_axis]} spanning lo..hi along
@@ -346,10 +358,12 @@ dpso_status dpso_run_batch(const dpso_batch_item *items, int32_t count, int32_t 
 /* Progress counters. Synchronises `stream`. */
 dpso_status dpso_get_info(const void *d_state, dpso_info *info, void *stream);
 
-/* Global best: h_tour (host [n]) receives the tour as stored, *h_cost its
- * cost, *h_generation the generations completed; h_trace (nullable, host
- * [generation + 1]) the global-best cost after each generation. Any output
- * pointer may be NULL. Synchronises `stream`. */
+/* The answer of the method: its global best (the particle with the best
+ * fitness, kept across generations; pseudo code of Sect. 3.3). h_tour (host
+ * [n]) receives the tour as stored, *h_cost its cost, *h_generation the
+ * generations completed; h_trace (nullable, host [generation + 1]) the
+ * global-best cost after each generation. Any output pointer may be NULL.
+ * Synchronises `stream`. */
 dpso_status dpso_get_best(const void *d_state, int32_t *h_tour, int64_t *h_cost,
                           int32_t *h_generation, int64_t *h_trace, void *stream);
 

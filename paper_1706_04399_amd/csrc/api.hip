@@ -483,6 +483,18 @@ size_t dpso_state_bytes(int32_t n, int32_t swarm_size, int32_t max_generations)
     return dpso::make_layout(n, swarm_size, max_generations + 1).total;
 }
 
+dpso_status dpso_request_footprint(int32_t n, const dpso_params *params, size_t budget, size_t *bytes)
+{
+    dpso_status st = check_params(params, n);
+    if (st) return st;
+    const size_t need = dpso::make_layout(n, params->swarm_size, params->max_generations + 1).total +
+                        size_t(n) * size_t(n) * 4;
+    if (bytes) *bytes = need;
+    if (need > budget)
+        return fail(DPSO_E_ADMIT, "request needs %zu bytes of device memory, the budget is %zu", need, budget);
+    return ok();
+}
+
 size_t dpso_dist_work_bytes(int32_t n, int32_t n_boxes)
 {
     if (n < 1 || n > DPSO_MAX_N || n_boxes < 0 || int64_t(n) + 8 * int64_t(n_boxes) > DPSO_MAX_GRAPH)

@@ -15,7 +15,7 @@ import torch  # loaded first so libdpso binds to the HIP runtime torch already u
 
 _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libdpso.so")
 
-OK, E_INVAL, E_RANGE, E_NOMEM, E_DEVICE, E_STATE = 0, -1, -2, -3, -4, -5
+OK, E_INVAL, E_RANGE, E_NOMEM, E_DEVICE, E_STATE, E_ADMIT = 0, -1, -2, -3, -4, -5, -6
 D_INF = (1 << 28) - 1
 NOALLOC_WORK_BYTES = 32 << 20   # static workspace of dpso_build_dist_noalloc
 MAX_N = 4096
@@ -91,6 +91,7 @@ EXPORTS = {
     "dpso_state_bytes": (C.c_size_t, [C.c_int32, C.c_int32, C.c_int32]),
     "dpso_dist_work_bytes": (C.c_size_t, [C.c_int32, C.c_int32]),
     "dpso_build_dist_noalloc": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "dpso_request_footprint": (C.c_int32, [C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p]),
     "dpso_build_dist": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
     "dpso_init_nn": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_size_t,
                                  C.c_void_p]),
@@ -228,6 +229,17 @@ def check_dist(D: torch.Tensor, stream=None) -> int:
     if st not in (OK, E_RANGE):
         _check(st)
     return int(bad.value)
+
+
+def request_footprint(n: int, params, budget: int):
+    """(status, bytes): the device bytes a served request holds while resident
+    (swarm state and distance matrix) and OK, or E_ADMIT if they exceed the
+    budget; other statuses raise."""
+    nbytes = C.c_size_t(0)
+    st = lib().dpso_request_footprint(int(n), C.byref(_params(params)), int(budget), C.byref(nbytes))
+    if st not in (OK, E_ADMIT):
+        _check(st)
+    return st, int(nbytes.value)
 
 
 def new_state(n: int, params, device="cuda") -> torch.Tensor:
@@ -370,15 +382,21 @@ def batch_work_bytes(count: int) -> int:
 class Batch:
     """Many independent swarms driven by batched launches.
 
-    members: list of (D tensor, params dict); states are allocated here."""
+    members: list of (D tensor, params dict). `states` (optional) are existing
+    state buffers, one per member (resident swarms resume from them); `work`
+    (optional) a device buffer of at least batch_work_bytes(len(members))
+    bytes for the batch tables. Whatever is not given is allocated here."""
 
-    def __init__(self, members, stream=None):
+    def __init__(self, members, stream=None, states=None, work: torch.Tensor | None = None):
         self.stream = stream
         self.members = [(D, dict(p)) for D, p in members]
         dev = self.members[0][0].device
-        self.states = [new_state(D.shape[0], p, dev) for D, p in self.members]
+        self.states = list(states) if states is not None else \
+            [new_state(D.shape[0], p, dev) for D, p in self.members]
         n = len(self.members)
-        self.work = torch.empty(max(batch_work_bytes(n), 1), dtype=torch.uint8, device=dev)
+        if work is None or work.numel() < batch_work_bytes(n):
+            work = torch.empty(max(batch_work_bytes(n), 1), dtype=torch.uint8, device=dev)
+        self.work = work
         self.items = (BatchItem * n)()
         for i, ((D, p), st) in enumerate(zip(self.members, self.states)):
             self.items[i] = BatchItem(_dev(D, torch.int32).value, D.shape[0], _params(p),

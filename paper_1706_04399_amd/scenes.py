@@ -197,6 +197,29 @@ def serpentine(walls: int, gap_mm: int = 2_000_000, half_mm: int = 65_000_000) -
     return Scene(np.array(vp, np.int32), np.array(boxes, np.int32).reshape(-1, 6), 0, f"serpentine{walls}")
 
 
+def moved_box(scene: Scene, seed: int, shift_mm: int = 2000, tries: int = 32) -> Scene:
+    """The scene with one obstacle moved (a changed site for re-planning): box
+    k = seed mod b is shifted by a random offset of up to `shift_mm` per axis,
+    redrawn while a viewpoint would fall inside its inflated volume; after
+    `tries` failed draws the scene is returned unchanged. Scenes without
+    boxes are returned unchanged."""
+    b = len(scene.boxes_mm)
+    if b == 0:
+        return scene
+    rng = np.random.default_rng(seed)
+    k = seed % b
+    boxes = [tuple(int(v) for v in row) for row in scene.boxes_mm]
+    for _ in range(tries):
+        d = rng.integers(-shift_mm, shift_mm + 1, size=3)
+        moved = tuple(boxes[k][a] + int(d[a % 3]) for a in range(6))
+        if not any(_inside_inflated(tuple(int(v) for v in p), [moved], scene.clearance_mm)
+                   for p in scene.vp_mm):
+            boxes[k] = moved
+            return Scene(scene.vp_mm.copy(), np.array(boxes, np.int32), scene.clearance_mm,
+                         scene.name)
+    return scene
+
+
 def random_points(n, seed, extent_mm=20_000, n_boxes=0, clearance_mm=CLEARANCE_MM) -> Scene:
     """Uniform points in a cube, optionally with random boxes (sides 500..3000)."""
     rng = np.random.default_rng(seed)

@@ -1,22 +1,30 @@
-"""Online re-planning: solves arrive over time and are served in batches.
+"""Online re-planning: plan requests arrive over time and are served in batches.
 
 The paper asks the planner to be fast enough for online re-planning
 (criterion (iv) of Sect. 1; re-planning is named again in Sect. 5). This module
 serves a stream of plan requests on one GPU:
 
+* a request names a site (a scene: viewpoints and obstacles) and its
+  obstacle version; a site's distance matrix and swarm stay resident on the
+  device between requests. A request on a resident site with unchanged
+  obstacles resumes that swarm for its generations (re-planning from where
+  the last plan left off); a changed obstacle rebuilds the distance matrix in
+  place and restarts the swarm on it; a swarm whose trace capacity is spent
+  restarts on the cached matrix; a site that is not resident is planned from
+  scratch;
 * requests wait in arrival order; each time the GPU is free the scheduler
-  admits the waiting requests first come, first served, while the device
-  footprint of the batch (swarm state + distance matrix + distance-builder
-  workspace) stays within a budget; a request whose footprint alone exceeds
-  the budget can never run and is rejected (status ``E_ADMIT``), so the head
-  of the queue always fits and every admission round admits at least one;
-* the admitted requests run as one batch (`dpso_run_batch`), distance
-  matrices of scenes already resident are reused (re-planning on a known
-  scene skips the distance build);
+  admits the waiting requests first come, first served while the device
+  memory of the resident sites plus the new ones stays within a budget,
+  evicting the least recently used sites that are not in the batch; a request
+  whose own footprint exceeds the budget can never run and is rejected
+  (status ``E_ADMIT``, decided by the library's ``dpso_request_footprint``),
+  so the head of the queue always fits; a second request for a site already
+  in the batch waits for the next one;
+* the admitted requests run as one batch (`dpso_run_batch`);
 * latency is completion time minus arrival time.
 
-The scheduler is independent of the executor, so admission and accounting
-are tested on the CPU with a stub executor and a fake clock.
+The scheduler is independent of the executor, so admission, residency and
+accounting are tested on the CPU with a stub executor and a fake clock.
 """
 from __future__ import annotations
 
@@ -28,6 +36,7 @@ import time
 import numpy as np
 
 from . import scenes
+from .dpso import E_ADMIT, OK   # status codes of the C ABI (DPSO_OK, DPSO_E_ADMIT)
 
 
 @dataclasses.dataclass
@@ -35,15 +44,18 @@ class Request:
     rid: int
     arrival: float          # seconds after the start of the stream
     scene: "scenes.Scene"
-    params: dict
-    key: str = ""           # scene identity for the distance-matrix cache
+    params: dict            # swarm parameters; max_generations is the swarm's capacity
+    key: str = ""           # site identity ("": a one-off scene, not kept resident)
+    version: int = 0        # obstacle version of the site
+    generations: int = 0    # generations this request runs (0: params["max_generations"])
 
     @property
     def n(self) -> int:
         return self.scene.n
 
-
-E_ADMIT = -6   # rejected at admission: footprint above the whole budget
+    @property
+    def run_generations(self) -> int:
+        return self.generations or self.params["max_generations"]
 
 
 @dataclasses.dataclass
@@ -55,7 +67,10 @@ class Record:
     done: float
     cost: int
     batch: int
-    status: int = 0   # 0 served, E_ADMIT rejected
+    status: int = OK        # OK served, E_ADMIT rejected
+    action: str = ""        # plan, resume, rebuild, restart (see GpuExecutor.solve)
+    generation: int = -1    # generations the swarm has completed
+    tour: np.ndarray | None = None
 
     @property
     def latency(self) -> float:
@@ -63,51 +78,112 @@ class Record:
 
 
 def poisson_requests(count, rate, seed=5, n_lo=50, n_hi=800, swarm=512, generations=300):
-    """Arrivals of a Poisson process of the given rate; request r has n
-    log-uniform in [n_lo, n_hi], alternates facade and bridge scenes, and uses
-    scene seed r."""
+    """One-off plans: arrivals of a Poisson process of the given rate; request r
+    has n log-uniform in [n_lo, n_hi], alternates facade and bridge scenes,
+    and uses scene seed r."""
     rng = np.random.default_rng(seed)
     gaps = rng.exponential(1.0 / rate, size=count)
     arrivals = np.cumsum(gaps) - gaps[0]
     reqs = []
     for r in range(count):
         n = int(round(math.exp(rng.uniform(math.log(n_lo), math.log(n_hi)))))
-        if r % 2 == 0:
-            h = int(round(math.sqrt(0.9e6 * n)))
-            sc = scenes.facade(n, int(round(h * 10 / 3)), h, int(round(n / 50)), seed=r)
-        else:
-            sc = scenes.bridge(n, int(round(40_000 * n / 200)), max(1, int(round(6 * n / 200))), seed=r)
         prm = scenes.swarm_params(swarm, generations, seed=0, instance=r)
-        reqs.append(Request(r, float(arrivals[r]), sc, prm, key=f"scene{r}"))
+        reqs.append(Request(r, float(arrivals[r]), _site_scene(r, n), prm))
+    return reqs
+
+
+def _site_scene(s: int, n: int) -> "scenes.Scene":
+    if s % 2 == 0:
+        h = int(round(math.sqrt(0.9e6 * n)))
+        return scenes.facade(n, int(round(h * 10 / 3)), h, int(round(n / 50)), seed=s)
+    return scenes.bridge(n, int(round(40_000 * n / 200)), max(1, int(round(6 * n / 200))), seed=s)
+
+
+def replan_requests(count, rate, seed=5, sites=100, n_lo=50, n_hi=800, swarm=512, generations=300,
+                    change_permille=200, capacity_runs=32):
+    """Re-planning stream: Poisson arrivals at `rate`/s over `sites` sites.
+    Site s has n log-uniform in [n_lo, n_hi] (drawn first, in site order) and
+    alternates facade and bridge scenes with scene seed s. Request r picks a
+    site uniformly; on a site seen before, with probability
+    change_permille / 1000 one of its obstacles has moved since (a new
+    obstacle version, `scenes.moved_box`). Every request runs `generations`
+    generations; a swarm holds `capacity_runs` such runs before it restarts."""
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / rate, size=count)
+    arrivals = np.cumsum(gaps) - gaps[0]
+    site_n = [int(round(math.exp(rng.uniform(math.log(n_lo), math.log(n_hi))))) for _ in range(sites)]
+    base, version, seen, current = {}, [0] * sites, set(), {}
+    reqs = []
+    for r in range(count):
+        s = int(rng.integers(sites))
+        if s in seen and int(rng.integers(1000)) < change_permille:
+            version[s] += 1
+        seen.add(s)
+        if s not in base:
+            base[s] = _site_scene(s, site_n[s])
+            current[s] = (0, base[s])
+        if current[s][0] != version[s]:
+            current[s] = (version[s], scenes.moved_box(base[s], seed=1_000_003 * s + version[s]))
+        prm = scenes.swarm_params(swarm, generations * capacity_runs, seed=0, instance=s)
+        reqs.append(Request(r, float(arrivals[r]), current[s][1], prm, key=f"site{s}",
+                            version=version[s], generations=generations))
     return reqs
 
 
 class Scheduler:
-    """First come, first served admission under a device-memory budget.
-    Requests that exceed the budget on their own are moved to `rejected`."""
+    """First come, first served admission under a device-memory budget, with
+    resident sites evicted least recently used first.
+
+    footprint(req) -> (status, bytes): the bytes a request holds while
+    resident, and E_ADMIT if they exceed the whole budget (such requests go to
+    `rejected`). Evicted site keys collect in `evicted` for the executor."""
 
     def __init__(self, budget_bytes: int, footprint, max_batch: int = 1024):
         self.budget = int(budget_bytes)
         self.footprint = footprint
         self.max_batch = int(max_batch)
-        self.rejected = []
+        self.rejected, self.evicted = [], []
+        self.resident = collections.OrderedDict()   # site key -> bytes, least recent first
+        self.n_evicted = 0
+
+    def resident_bytes(self) -> int:
+        return sum(self.resident.values())
 
     def admit(self, queue: collections.deque) -> list:
-        batch, used = [], 0
+        batch, keys, new = [], set(), 0
         while queue and len(batch) < self.max_batch:
-            need = self.footprint(queue[0])
-            if need > self.budget:
+            req = queue[0]
+            status, need = self.footprint(req)
+            if status == E_ADMIT:
                 self.rejected.append(queue.popleft())
                 continue
-            if used + need > self.budget:
+            if req.key and req.key in keys:
+                break                        # its swarm runs in this batch already
+            cost = 0 if req.key and req.key in self.resident else need
+            while self.resident_bytes() + new + cost > self.budget:
+                victim = next((k for k in self.resident if k not in keys), None)
+                if victim is None:
+                    break
+                del self.resident[victim]
+                self.evicted.append(victim)
+                self.n_evicted += 1
+            if self.resident_bytes() + new + cost > self.budget:
                 break
             batch.append(queue.popleft())
-            used += need
+            if req.key:                      # resident from now on, most recently used
+                keys.add(req.key)
+                self.resident[req.key] = self.resident.pop(req.key, need)
+            else:                            # a one-off scene holds memory while it runs
+                new += need
         return batch
 
 
 def serve(requests, executor, scheduler: Scheduler, clock=time.perf_counter, sleep=time.sleep):
-    """Serves `requests` (sorted by arrival) in real time; returns Records."""
+    """Serves `requests` (sorted by arrival) in real time; returns Records.
+
+    executor.solve(batch) returns one dict per request with "cost" and
+    optionally "action", "generation" and "tour"; executor.evict(keys), if
+    present, releases the sites the scheduler evicted."""
     pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
     queue = collections.deque()
     records, nbatch = [], 0
@@ -122,68 +198,125 @@ def serve(requests, executor, scheduler: Scheduler, clock=time.perf_counter, sle
         batch = scheduler.admit(queue)
         for req in scheduler.rejected:
             now = clock() - t0
-            records.append(Record(req.rid, req.n, req.arrival, now, now, -1, -1, E_ADMIT))
+            records.append(Record(req.rid, req.n, req.arrival, now, now, -1, -1, E_ADMIT, "rejected"))
         scheduler.rejected.clear()
+        if scheduler.evicted:
+            if hasattr(executor, "evict"):
+                executor.evict(list(scheduler.evicted))
+            scheduler.evicted.clear()
         if not batch:
             continue
         start = clock() - t0
-        costs = executor.solve(batch)
+        results = executor.solve(batch)
         done = clock() - t0
-        for req, cost in zip(batch, costs):
-            records.append(Record(req.rid, req.n, req.arrival, start, done, int(cost), nbatch))
+        for req, res in zip(batch, results):
+            records.append(Record(req.rid, req.n, req.arrival, start, done, int(res["cost"]), nbatch,
+                                  OK, res.get("action", ""), int(res.get("generation", -1)),
+                                  res.get("tour")))
         nbatch += 1
     return records
 
 
-def summary(records, warmup: int = 0) -> dict:
-    """Latency percentiles and throughput over the served requests after
-    `warmup` (rejected requests are counted, not timed)."""
+def summary(records, warmup: int = 0, scheduler: Scheduler | None = None) -> dict:
+    """Latency percentiles, throughput and residency over the served requests
+    after `warmup` (rejected requests are counted, not timed)."""
     after = sorted(records, key=lambda r: r.rid)[warmup:]
-    rs = [r for r in after if r.status == 0]
+    rs = [r for r in after if r.status == OK]
     if not rs:
         return {"requests": 0, "rejected": len(after)}
     lat = np.array([r.latency for r in rs])
     span = max(r.done for r in rs) - min(r.arrival for r in rs)
-    return {"requests": len(rs), "p50_ms": float(np.percentile(lat, 50) * 1e3),
-            "p99_ms": float(np.percentile(lat, 99) * 1e3), "mean_ms": float(lat.mean() * 1e3),
-            "max_ms": float(lat.max() * 1e3), "solves_per_s": len(rs) / span if span > 0 else 0.0,
-            "batches": len({r.batch for r in rs}), "rejected": len(after) - len(rs),
-            "mean_batch": len(rs) / max(1, len({r.batch for r in rs}))}
+    acts = collections.Counter(r.action for r in rs)
+    out = {"requests": len(rs), "p50_ms": float(np.percentile(lat, 50) * 1e3),
+           "p99_ms": float(np.percentile(lat, 99) * 1e3), "mean_ms": float(lat.mean() * 1e3),
+           "max_ms": float(lat.max() * 1e3), "solves_per_s": len(rs) / span if span > 0 else 0.0,
+           "batches": len({r.batch for r in rs}), "rejected": len(after) - len(rs),
+           "mean_batch": len(rs) / max(1, len({r.batch for r in rs})),
+           "actions": dict(sorted(acts.items())),
+           # the swarm resumed from device memory / the distance matrix reused
+           "state_hit_rate": acts["resume"] / len(rs),
+           "dist_hit_rate": (acts["resume"] + acts["restart"]) / len(rs)}
+    if scheduler is not None:
+        out["evictions"] = scheduler.n_evicted
+    return out
+
+
+@dataclasses.dataclass
+class _Site:
+    version: int
+    D: object               # device int32 [n][n]
+    state: object           # device swarm state
+    params: dict
+    t: int = 0              # generations completed
 
 
 class GpuExecutor:
-    """Runs an admitted batch with the batched C ABI; keeps distance matrices
-    of recent scenes resident on the device (a bounded cache)."""
+    """Runs admitted batches with the batched C ABI. Sites keep their distance
+    matrix and swarm state in device memory until evicted; distance matrices
+    are built with the builder's static workspace (no allocation)."""
 
-    def __init__(self, stream=None, cache_scenes: int = 64):
+    def __init__(self, budget_bytes: int, stream=None):
         import torch
         from . import dpso
         self.dpso, self.torch = dpso, torch
+        self.budget = int(budget_bytes)
         self.stream = stream if stream is not None else torch.cuda.Stream()
-        self.cache = collections.OrderedDict()
-        self.cache_scenes = cache_scenes
+        self.sites = {}
+        self.work = None
 
-    def footprint(self, req: Request) -> int:
-        d = self.dpso
-        n, p = req.n, req.params
-        return (d.state_bytes(n, p["swarm_size"], p["max_generations"]) + 4 * n * n +
-                d.dist_work_bytes(n, len(req.scene.boxes_mm)))
+    def footprint(self, req: Request):
+        return self.dpso.request_footprint(req.n, req.params, self.budget)
 
-    def _dist(self, req: Request):
-        D = self.cache.get(req.key)
-        if D is None:
-            D = self.dpso.build_dist(req.scene, stream=self.stream)
-            self.cache[req.key] = D
-            while len(self.cache) > self.cache_scenes:
-                self.cache.popitem(last=False)
-        else:
-            self.cache.move_to_end(req.key)
-        return D
+    def evict(self, keys):
+        for k in keys:
+            self.sites.pop(k, None)
+
+    def _work(self, count):
+        need = self.dpso.batch_work_bytes(count)
+        if self.work is None or self.work.numel() < need:
+            self.work = self.torch.empty(max(need, 1 << 16), dtype=self.torch.uint8, device="cuda")
+        return self.work
 
     def solve(self, batch):
-        d = self.dpso
-        Ds = [self._dist(r) for r in batch]
-        b = d.Batch([(D, r.params) for D, r in zip(Ds, batch)], stream=self.stream)
-        # each swarm stops at its own max_generations
-        b.init().run(max(r.params["max_generations"] for r in batch))
-        return [d.get_best(st, self.stream)[1] for st in b.states]
+        """Actions: "plan" (site not resident: build the matrix, start a swarm),
+        "rebuild" (obstacles changed: rebuild the matrix in place, restart the
+        swarm), "restart" (the swarm's capacity is spent: restart it on the
+        cached matrix), "resume" (run the resident swarm further)."""
+        d, torch = self.dpso, self.torch
+        sites, actions, cold = [], [], []
+        for req in batch:
+            G = req.run_generations
+            site = self.sites.get(req.key) if req.key else None
+            if site is None:
+                D = torch.empty((req.n, req.n), dtype=torch.int32, device="cuda")
+                d.build_dist_noalloc(req.scene, out=D, stream=self.stream)
+                site = _Site(req.version, D, d.new_state(req.n, req.params), dict(req.params))
+                if req.key:
+                    self.sites[req.key] = site
+                act = "plan"
+            elif site.version != req.version:
+                d.build_dist_noalloc(req.scene, out=site.D, stream=self.stream)
+                site.version = req.version
+                act = "rebuild"
+            elif site.t + G > site.params["max_generations"]:
+                act = "restart"
+            else:
+                act = "resume"
+            if act != "resume":
+                cold.append(site)
+                site.t = 0
+            site.t += G
+            sites.append(site)
+            actions.append(act)
+        if cold:
+            d.Batch([(s.D, s.params) for s in cold], stream=self.stream,
+                    states=[s.state for s in cold], work=self._work(len(cold))).init()
+        for G in sorted({r.run_generations for r in batch}):
+            group = [s for s, r in zip(sites, batch) if r.run_generations == G]
+            d.Batch([(s.D, s.params) for s in group], stream=self.stream,
+                    states=[s.state for s in group], work=self._work(len(group))).run(G)
+        out = []
+        for site, act in zip(sites, actions):
+            tour, cost, gen, _ = d.get_best(site.state, self.stream)
+            out.append({"cost": cost, "action": act, "generation": gen, "tour": tour})
+        return out

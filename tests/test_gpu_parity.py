@@ -510,24 +510,44 @@ def test_batch_matches_oracle(dp, graph):
         assert not bad, f"instance {k} (n={D.shape[0]}): {bad}"
 
 
-def test_served_results_equal_single_solves(dp):
-    """A short stream through the re-planning server: every served plan equals
-    the plan of solving that request alone (and a tight budget forces several
-    batches)."""
+def test_served_replans_match_oracle(dp):
+    """A short re-planning stream through the server (5 sites, obstacle
+    changes, swarm capacity of 3 runs, a budget that holds the two largest
+    sites, so that sites are evicted): every served plan equals the oracle replaying the same sequence
+    of actions per site (a fresh swarm for plan / rebuild / restart on the
+    request's scene, the site's previous swarm run further for resume)."""
+    import collections
     from paper_1706_04399_amd import serve
-    reqs = serve.poisson_requests(12, rate=400.0, seed=9, n_lo=20, n_hi=120, swarm=32,
-                                  generations=15)
-    ex = serve.GpuExecutor()
-    budget = 3 * max(ex.footprint(r) for r in reqs)
-    recs = serve.serve(reqs, ex, serve.Scheduler(budget, ex.footprint))
-    assert sorted(r.rid for r in recs) == list(range(12))
-    assert len({r.batch for r in recs}) >= 4
-    for rec in recs:
+    reqs = serve.replan_requests(40, rate=400.0, seed=9, sites=5, n_lo=20, n_hi=120, swarm=32,
+                                 generations=15, change_permille=300, capacity_runs=3)
+    sizes = sorted({r.key: dp.request_footprint(r.n, r.params, 1 << 40)[1] for r in reqs}.values())
+    budget = sizes[-1] + sizes[-2]             # the two largest sites fit together, not all five
+    ex = serve.GpuExecutor(budget_bytes=budget)
+    sched = serve.Scheduler(budget, ex.footprint)
+    note("served re-planning stream of 40 requests against the oracle")
+    recs = serve.serve(reqs, ex, sched)
+    assert sorted(r.rid for r in recs) == list(range(40)) and all(r.status == 0 for r in recs)
+    acts = collections.Counter(r.action for r in recs)
+    assert acts["resume"] and acts["rebuild"] and acts["restart"] and sched.n_evicted > 0, acts
+    sites = {}
+    for rec in sorted(recs, key=lambda r: r.rid):
         req = reqs[rec.rid]
-        D = dp.build_dist(req.scene)
-        st = dp.init_nn(D, req.params)
-        dp.run(D, req.params, st, req.params["max_generations"])
-        assert dp.get_best(st)[1] == rec.cost, rec.rid
+        G, cap = req.generations, req.params["max_generations"]
+        site = sites.get(req.key)
+        if rec.action == "resume":
+            assert site is not None and site["version"] == req.version and site["st"].t + G <= cap
+        else:
+            if rec.action == "rebuild":
+                assert site is not None and site["version"] != req.version
+            if rec.action == "restart":
+                assert site is not None and site["version"] == req.version and site["st"].t + G > cap
+            D = oracle.build_dist(req.scene)
+            site = {"version": req.version, "D": D, "st": oracle.new_state(D, req.params)}
+            sites[req.key] = site
+        oracle.run(site["D"], req.params, site["st"], G)
+        o = site["st"]
+        assert (rec.cost, rec.generation) == (o.FG, o.t), (rec.rid, rec.action)
+        assert np.array_equal(rec.tour, o.G), (rec.rid, rec.action)
 
 
 def _costs(D, tours):

@@ -41,6 +41,26 @@ def test_binding_covers_exports(dp):
     assert set(dp.EXPORTS) == set(declared_functions())
 
 
+def test_status_codes_match_header(dp):
+    src = open(HEADER).read()
+    codes = dict(re.findall(r"#define DPSO_(OK|E_[A-Z]+)\s+\(?(-?\d+)\)?", src))
+    assert set(codes) == {"OK", "E_INVAL", "E_RANGE", "E_NOMEM", "E_DEVICE", "E_STATE", "E_ADMIT"}
+    for name, value in codes.items():
+        assert getattr(dp, name) == int(value), name
+
+
+def test_request_footprint(dp):
+    """State plus distance matrix; E_ADMIT above the budget, on the host."""
+    p = _params()
+    need = dp.state_bytes(30, 64, 200) + 30 * 30 * 4
+    assert dp.request_footprint(30, p, need) == (dp.OK, need)
+    assert dp.request_footprint(30, p, need - 1) == (dp.E_ADMIT, need)
+    assert "budget" in dp.lib().dpso_last_error().decode()
+    with pytest.raises(dp.DpsoError) as ei:
+        dp.request_footprint(0, p, 1 << 30)
+    assert ei.value.status == dp.E_INVAL
+
+
 def _params(**kw):
     from paper_1706_04399_amd import scenes
     return scenes.swarm_params(64, 200, **kw)

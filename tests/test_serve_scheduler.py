@@ -29,30 +29,40 @@ class StubExecutor:
     def solve(self, batch):
         self.batches.append([r.rid for r in batch])
         self.clock.t += self.over + self.per * len(batch)
-        return [r.n for r in batch]
+        return [{"cost": r.n} for r in batch]
 
 
-def _reqs(arrivals, n=10):
+def _reqs(arrivals, n=10, keys=None):
     sc = scenes.line(list(range(n)))
-    return [serve.Request(i, a, sc, scenes.swarm_params(4, 3)) for i, a in enumerate(arrivals)]
+    keys = keys or [""] * len(arrivals)
+    return [serve.Request(i, a, sc, scenes.swarm_params(4, 3), key=k)
+            for i, (a, k) in enumerate(zip(arrivals, keys))]
+
+
+def fp(budget, size):
+    """A footprint function as the executor's: (E_ADMIT if above the budget, bytes)."""
+    def f(r):
+        b = size(r) if callable(size) else size
+        return (serve.E_ADMIT if b > budget else serve.OK), b
+    return f
 
 
 def test_admission_respects_budget_and_order():
-    sched = serve.Scheduler(budget_bytes=250, footprint=lambda r: 100, max_batch=10)
+    sched = serve.Scheduler(budget_bytes=250, footprint=fp(250, 100), max_batch=10)
     q = collections.deque(_reqs([0.0] * 5))
     assert [r.rid for r in sched.admit(q)] == [0, 1]
     assert [r.rid for r in sched.admit(q)] == [2, 3]
     assert [r.rid for r in sched.admit(q)] == [4]
-    big = serve.Scheduler(budget_bytes=50, footprint=lambda r: 100)
+    big = serve.Scheduler(budget_bytes=50, footprint=fp(50, 100))
     q = collections.deque(_reqs([0.0] * 2))
     assert big.admit(q) == [] and not q                  # can never fit: rejected
     assert [r.rid for r in big.rejected] == [0, 1]
-    mixed = serve.Scheduler(budget_bytes=150, footprint=lambda r: 200 if r.rid == 1 else 100)
+    mixed = serve.Scheduler(budget_bytes=150, footprint=fp(150, lambda r: 200 if r.rid == 1 else 100))
     q = collections.deque(_reqs([0.0] * 4))
     assert [r.rid for r in mixed.admit(q)] == [0]        # 1 rejected, 2 does not fit beside 0
     assert [r.rid for r in mixed.rejected] == [1]
     assert [r.rid for r in mixed.admit(q)] == [2]
-    capped = serve.Scheduler(budget_bytes=10 ** 9, footprint=lambda r: 1, max_batch=3)
+    capped = serve.Scheduler(budget_bytes=10 ** 9, footprint=fp(10 ** 9, 1), max_batch=3)
     q = collections.deque(_reqs([0.0] * 7))
     assert [len(capped.admit(q)) for _ in range(3)] == [3, 3, 1]
 
@@ -60,7 +70,7 @@ def test_admission_respects_budget_and_order():
 def test_serve_batches_waiting_requests_and_accounts_latency():
     clock = FakeClock()
     ex = StubExecutor(clock, per_request=0.01, overhead=0.005)
-    sched = serve.Scheduler(budget_bytes=10 ** 9, footprint=lambda r: 1)
+    sched = serve.Scheduler(budget_bytes=10 ** 9, footprint=fp(10 ** 9, 1))
     reqs = _reqs([0.0, 0.001, 0.002, 0.5, 0.5001])
     recs = serve.serve(reqs, ex, sched, clock=clock, sleep=clock.sleep)
     # request 0 runs alone; 1 and 2 arrived meanwhile and run together; the
@@ -89,13 +99,79 @@ def test_poisson_requests_shape():
     assert arr[0] == 0.0 and (np.diff(arr) >= 0).all()
     assert all(50 <= r.n <= 800 for r in reqs)
     assert 0.2 < arr[-1] < 2.0                    # about 40 / 50 s
-    assert len({r.key for r in reqs}) == 40
+    assert {r.key for r in reqs} == {""}            # one-off scenes, never resident
+
+
+def test_resident_sites_cost_nothing_and_evict_least_recent_first():
+    sched = serve.Scheduler(budget_bytes=300, footprint=fp(300, 100))
+    q = collections.deque(_reqs([0.0] * 3, keys=["a", "b", "c"]))
+    assert [r.rid for r in sched.admit(q)] == [0, 1, 2]
+    assert list(sched.resident) == ["a", "b", "c"] and sched.resident_bytes() == 300
+    # a re-plan of a resident site needs no memory; "a" becomes most recent
+    q = collections.deque(_reqs([0.0], keys=["a"]))
+    assert [r.rid for r in sched.admit(q)] == [0] and not sched.evicted
+    assert list(sched.resident) == ["b", "c", "a"]
+    # a new site evicts the least recently used one that is not in the batch
+    q = collections.deque(_reqs([0.0, 0.0], keys=["b", "d"]))
+    assert [r.rid for r in sched.admit(q)] == [0, 1]
+    assert sched.evicted == ["c"] and list(sched.resident) == ["a", "b", "d"]
+    assert sched.n_evicted == 1
+
+
+def test_second_request_for_a_site_waits_for_the_next_batch():
+    sched = serve.Scheduler(budget_bytes=10 ** 6, footprint=fp(10 ** 6, 10))
+    q = collections.deque(_reqs([0.0] * 4, keys=["a", "b", "a", "c"]))
+    assert [r.rid for r in sched.admit(q)] == [0, 1]     # FCFS: stops at the second "a"
+    assert [r.rid for r in sched.admit(q)] == [2, 3]
+
+
+def test_sites_in_the_batch_are_never_evicted():
+    sched = serve.Scheduler(budget_bytes=200, footprint=fp(200, 100))
+    q = collections.deque(_reqs([0.0] * 3, keys=["a", "b", "c"]))
+    assert [r.rid for r in sched.admit(q)] == [0, 1]     # "c" must wait: a and b are running
+    assert not sched.evicted
+    assert [r.rid for r in sched.admit(q)] == [2] and sched.evicted == ["a"]
+
+
+def test_replan_requests_shape():
+    reqs = serve.replan_requests(300, rate=50.0, seed=5, sites=20, n_lo=20, n_hi=60, swarm=8,
+                                 generations=10, change_permille=300, capacity_runs=4)
+    arr = np.array([r.arrival for r in reqs])
+    assert arr[0] == 0.0 and (np.diff(arr) >= 0).all()
+    by_site = {}
+    for r in reqs:
+        by_site.setdefault(r.key, []).append(r)
+        assert r.generations == 10 and r.params["max_generations"] == 40
+    assert len(by_site) == 20
+    changes = 0
+    for key, rs in by_site.items():
+        assert len({r.n for r in rs}) == 1 and all(20 <= r.n <= 60 for r in rs)
+        assert rs[0].version == 0
+        for a, b in zip(rs, rs[1:]):
+            assert b.version in (a.version, a.version + 1)
+            same = np.array_equal(a.scene.boxes_mm, b.scene.boxes_mm)
+            assert same or b.version != a.version          # obstacles change only with a new version
+            assert np.array_equal(a.scene.vp_mm, b.scene.vp_mm)
+            changes += b.version != a.version
+    assert 0.2 < changes / (len(reqs) - 20) < 0.4
+
+
+def test_moved_box_keeps_viewpoints_outside_and_moves_one_box():
+    sc = scenes.facade(60, 20_000, 6_000, 4, seed=3)
+    for seed in range(12):
+        mv = scenes.moved_box(sc, seed)
+        diff = (mv.boxes_mm != sc.boxes_mm).any(axis=1)
+        assert diff.sum() <= 1 and np.array_equal(mv.vp_mm, sc.vp_mm)
+        for p in mv.vp_mm:
+            for b in mv.boxes_mm:
+                c = mv.clearance_mm
+                assert not all(b[a] - c < p[a] < b[a + 3] + c for a in range(3))
 
 
 def test_rejected_requests_are_recorded_not_timed():
     clock = FakeClock()
     ex = StubExecutor(clock)
-    sched = serve.Scheduler(budget_bytes=100, footprint=lambda r: 1000 if r.rid % 2 else 10)
+    sched = serve.Scheduler(budget_bytes=100, footprint=fp(100, lambda r: 1000 if r.rid % 2 else 10))
     recs = serve.serve(_reqs([0.0, 0.0, 0.1, 0.2]), ex, sched, clock=clock, sleep=clock.sleep)
     by = {r.rid: r for r in recs}
     assert by[1].status == serve.E_ADMIT and by[3].status == serve.E_ADMIT
