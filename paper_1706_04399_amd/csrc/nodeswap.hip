@@ -45,6 +45,7 @@ __device__ __forceinline__ void node_swap_body(const Inst &I, int p)
     uint16_t *xg = st.X + size_t(p) * ns;
     for (int k = tid; k < n; k += kThreads) x[k] = xg[k];
     int64_t F = st.F[p];
+    const int64_t fp_old = st.FP[p];  // before the first barrier (thread 0 stores it at the end)
     int moves = 0, sweeps = 0;
     __syncthreads();
     for (;;) {
@@ -103,7 +104,7 @@ __device__ __forceinline__ void node_swap_body(const Inst &I, int p)
         if (kp.ee_max_moves > 0 && moves >= kp.ee_max_moves) break;
     }
     for (int k = tid; k < n; k += kThreads) xg[k] = x[k];
-    const bool better = F < st.FP[p];
+    const bool better = F < fp_old;
     if (better)
         for (int k = tid; k < n; k += kThreads) st.P[size_t(p) * ns + k] = x[k];
     if (tid == 0) {

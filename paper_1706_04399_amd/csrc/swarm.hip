@@ -573,6 +573,9 @@ __device__ __forceinline__ void move_body(const Inst &I, int part)
     }
     const int t = h->t + 1;
     const int n = st.n, ns = st.ns, tid = threadIdx.x;
+    // read before the first barrier: thread 0 stores the new personal-best
+    // cost at the end, after the last one
+    const int64_t fp_old = st.FP[part];
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int64_t redi[kMoveThreads / 64];
     __shared__ uint64_t draw0;  // first 64-bit word of stream (part, t, vel)
@@ -643,7 +646,7 @@ __device__ __forceinline__ void move_body(const Inst &I, int part)
         xo[k] = y[k];
     }
     const int64_t c = block_tour_cost(D, n, y, redi);
-    const bool better = c < st.FP[part];
+    const bool better = c < fp_old;
     if (better) DPSO_EACH(k) st.P[size_t(part) * ns + k] = y[k];
     if (tid == 0) {
         st.F[part] = c;
@@ -725,6 +728,7 @@ __device__ __forceinline__ void mut_apply_body(const Inst &I, int p)
     if (!mutation_generation(kp, t)) return;
     const int n = st.n;
     if (st.keep[p]) return;
+    const int64_t fp_old = st.FP[p];  // before the first barrier (thread 0 stores it at the end)
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int64_t redi[4];
     uint16_t *tour = reinterpret_cast<uint16_t *>(smem);
@@ -737,7 +741,7 @@ __device__ __forceinline__ void mut_apply_body(const Inst &I, int p)
         fisher_yates(tour, smem + size_t(st.ns) * 2, n, st.ns, kp, p, t, kMut);
     }
     const int64_t cf = store_particle(D, st, p, tour, false, redi);
-    const bool better = cf < st.FP[p];
+    const bool better = cf < fp_old;
     if (better)
         for (int k = threadIdx.x; k < n; k += blockDim.x) st.P[size_t(p) * st.ns + k] = tour[k];
     if (threadIdx.x == 0) {
@@ -762,6 +766,9 @@ __device__ __forceinline__ void gbest_body(const Inst &I)
     if (h->err) return;
     if (mode != 0 && h->done) return;
     if (mode == 2 && !h->ee_ran) return;
+    // read before the reduction's barriers: thread 0 stores the new cost at
+    // the end, after the last one
+    const int64_t fg_old = h->FG;
     __shared__ uint64_t red[16];
     uint64_t best = ~0ull;
     for (int p = threadIdx.x; p < st.S; p += blockDim.x) {
@@ -771,7 +778,7 @@ __device__ __forceinline__ void gbest_body(const Inst &I)
     best = block_min_u64(best, red);
     const int g = int(best & 0xffffu);
     const int64_t FPg = int64_t(best >> 16);
-    const bool better = mode == 0 || FPg < h->FG;
+    const bool better = mode == 0 || FPg < fg_old;
     __syncthreads();
     if (better)
         for (int k = threadIdx.x; k < st.n; k += blockDim.x) st.G[k] = st.P[size_t(g) * st.ns + k];

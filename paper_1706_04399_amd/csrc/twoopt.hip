@@ -42,6 +42,7 @@ __device__ __forceinline__ void twoopt_rows_body(const Inst &I, int p)
     uint16_t *xg = st.X + size_t(p) * ns;
     for (int k = tid; k < n; k += kThreads) x[k] = xg[k];
     int64_t F = st.F[p];
+    const int64_t fp_old = st.FP[p];  // before the first barrier (thread 0 stores it at the end)
     int moves = 0, sweeps = 0;
     __syncthreads();
     for (;;) {
@@ -92,7 +93,7 @@ __device__ __forceinline__ void twoopt_rows_body(const Inst &I, int p)
         if (kp.ee_max_moves > 0 && moves >= kp.ee_max_moves) break;
     }
     for (int k = tid; k < n; k += kThreads) xg[k] = x[k];
-    const bool better = F < st.FP[p];
+    const bool better = F < fp_old;
     if (better)
         for (int k = tid; k < n; k += kThreads) st.P[size_t(p) * ns + k] = x[k];
     if (tid == 0) {
@@ -243,12 +244,13 @@ struct WaveCfg {
     static constexpr int LDS_INTS = GUARD + 2 * STRIDE;
 };
 
-// One row of D in flight. Rows are read as aligned 16-byte chunks: when the
-// row starts `shift` ints past a 16-byte boundary (n not a multiple of 4),
-// the chunks start at the aligned-down address and each int is written to
+// One row of D in flight. Rows are staged as aligned 16-byte chunks: when
+// the row starts `shift` ints past a 16-byte boundary (n not a multiple of
+// 4), the chunks follow the aligned-down address and each int is written to
 // its own index of the LDS buffer, the few ints before 0 and past n landing
-// in the buffer's guard words. Chunk indices are clamped, so every load stays
-// inside the row's aligned span.
+// in the buffer's guard words. Chunk indices are clamped to the row's span,
+// and such rows are read int by int, only the ints of the row itself, since
+// the span can run past the end of the matrix.
 template <int MB, bool VEC4>
 struct RowPipe {
     static constexpr int R = VEC4 ? WaveCfg<MB, VEC4>::RV : WaveCfg<MB, VEC4>::RU;
@@ -264,13 +266,18 @@ struct RowPipe {
 #pragma unroll
             for (int k = 0; k < R; ++k) v[k] = s4[min(lane + 64 * k, q)];
         } else {
+            // the ints of the row's 16-byte span, those outside the row read
+            // as 0 (the span may run past the end of the matrix)
             shift = int(reinterpret_cast<uintptr_t>(src) & 15) >> 2;
-            // pointer arithmetic (not an integer round trip) keeps the
-            // global address space, so these are global, not flat, loads
-            const int4 *s4 = reinterpret_cast<const int4 *>(src - shift);
             const int q = ((shift + n + 3) >> 2) - 1;
 #pragma unroll
-            for (int k = 0; k < R; ++k) v[k] = s4[min(lane + 64 * k, q)];
+            for (int k = 0; k < R; ++k) {
+                const int e = 4 * min(lane + 64 * k, q) - shift;  // row index of the chunk's first int
+                v[k].x = e >= 0 && e < n ? src[e] : 0;
+                v[k].y = e + 1 >= 0 && e + 1 < n ? src[e + 1] : 0;
+                v[k].z = e + 2 >= 0 && e + 2 < n ? src[e + 2] : 0;
+                v[k].w = e + 3 >= 0 && e + 3 < n ? src[e + 3] : 0;
+            }
         }
     }
 
@@ -524,7 +531,7 @@ __device__ __forceinline__ void twoopt_wave_body(const Inst &I, int p)
 #pragma unroll
             for (int off = 32; off >= 1; off >>= 1) kmin = min(kmin, __shfl_xor(kmin, off, 64));
             const int amin = key_value(kmin);
-            if ((int64_t(amin) << shift) >= rho) break;  // no exchange improves
+            if (int64_t(amin) * (int64_t(1) << shift) >= rho) break;  // no exchange improves
             const int lim = amin + window;
             // exact (delta, i, j) over the rows left in the window
             uint64_t key = ~0ull;
