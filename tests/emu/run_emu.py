@@ -226,7 +226,8 @@ def case_serve(emu: Emu, count: int) -> bool:
     swarm 8, 6 generations per request, capacity of 3 runs, 30 % of re-plans
     after a moved obstacle, batches of up to 6 requests (one per site)."""
     from paper_1706_04399_amd import serve
-    reqs = serve.replan_requests(count, rate=50.0, seed=5, sites=12, n_lo=50, n_hi=800, swarm=8,
+    reqs = serve.replan_requests(count, rate=50.0, seed=int(os.environ.get("EMU_SEED", "5")), sites=12,
+                                 n_lo=50, n_hi=800, swarm=8,
                                  generations=6, change_permille=300, capacity_runs=3)
     sites, oracle_sites, ok = {}, {}, True
     pending = list(reqs)
