@@ -21,15 +21,6 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
-# Long runs of single-instance solves over hundreds of different n (the
-# one-at-a-time legs of the batched and served workloads) ended the GPU machine
-# twice, and reading the code has not shown a cause; until one is shown they
-# are not run. The batched path's one-instance-per-call figure stands in.
-PLAIN_LEGS_REFUSED = (
-    "bench.py: the one-at-a-time legs on the single-instance path (--batch N --plain-leg, "
-    "--serve N --plain) are refused: long runs of single-instance solves over many n ended "
-    "the GPU box twice with no cause shown yet (design notes, Measurement). The batched "
-    "workloads report a one-instance-per-call figure through the batched path instead.")
 VALU_LANE_OPS_PER_S = 256 * 4 * 16 * 2.4e9
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_facade1000.md")
 KERNEL_SRC = os.path.join(ROOT, "paper_1706_04399_amd", "csrc", "twoopt.hip")
@@ -189,11 +180,14 @@ def batch_cpu_baseline(sc, prm, generations: int, seconds: float, gpu_best):
             "identical_best_costs": same}
 
 
-def bench_batch(count: int, generations: int, cpu_seconds: float = 0.0, one_at_a_time: bool = True):
+def bench_batch(count: int, generations: int, cpu_seconds: float = 0.0, plain_leg: bool = True,
+                one_at_a_time: bool = False):
     """Batched workload: `count` independent instances (n log-uniform in
     [20, 500], facades and bridges by seed), swarm 256 each, edge exchange on
     stall. Solves/s of the batched path (one captured graph per run) against
-    the same instances solved one per call through the batched path
+    the plain single-instance path solving the same instances one after
+    another (`plain_leg`: dpso_init_nn and dpso_run per instance, on the same
+    stream), optionally the batched path with one instance per call
     (`one_at_a_time`), and the oracle on the host for about cpu_seconds (0:
     skipped)."""
     import torch
@@ -211,7 +205,22 @@ def bench_batch(count: int, generations: int, cpu_seconds: float = 0.0, one_at_a
     stream.synchronize()
     t_batch = time.perf_counter() - t0
     batch_best = [dpso.get_best(st, stream)[1] for st in b.states]
-    t_one, one_best = None, None
+    out = {}
+    if plain_leg:
+        states = [dpso.new_state(D.shape[0], p) for D, p in zip(Ds, prm)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for D, p, st in zip(Ds, prm, states):
+            dpso.init_nn(D, p, st, stream=stream)
+            dpso.run(D, p, st, generations, stream=stream)
+        stream.synchronize()
+        t_plain = time.perf_counter() - t0
+        plain_best = [dpso.get_best(st, stream)[1] for st in states]
+        del states
+        out.update({"plain_value": round(count / t_plain, 3),
+                    "plain_path": "dpso_init_nn + dpso_run per instance, one after another on one stream",
+                    "speedup_vs_plain": round(t_plain / t_batch, 3), "seconds_plain": round(t_plain, 3),
+                    "identical_results_plain": plain_best == batch_best})
     if one_at_a_time:
         t0 = time.perf_counter()
         ones = [dpso.Batch([(D, p)], stream=stream).init().run(generations) for D, p in zip(Ds, prm)]
@@ -219,16 +228,16 @@ def bench_batch(count: int, generations: int, cpu_seconds: float = 0.0, one_at_a
         t_one = time.perf_counter() - t0
         one_best = [o.best(0)[1] for o in ones]
         del ones
+        out.update({"one_per_call_value": round(count / t_one, 3),
+                    "one_per_call_path": "dpso_run_batch with one instance per call, in sequence",
+                    "speedup_vs_one_per_call": round(t_one / t_batch, 3),
+                    "identical_results_one_per_call": one_best == batch_best})
     ns = [s.n for s in sc]
     cpu = batch_cpu_baseline(sc, prm, generations, cpu_seconds, batch_best) if cpu_seconds > 0 else None
     return {
         "metric": "batched solves/s", "value": round(count / t_batch, 3), "unit": "solves/s",
-        "one_at_a_time_value": round(count / t_one, 3) if t_one else None,
-        "one_at_a_time_path": "dpso_run_batch with one instance per call, in sequence",
-        "speedup_vs_one_at_a_time": round(t_one / t_batch, 3) if t_one else None,
-        "seconds_batched": round(t_batch, 3), "seconds_one_at_a_time": round(t_one, 3) if t_one else None,
+        "seconds_batched": round(t_batch, 3), **out,
         "particle_iters_per_s": round(256 * generations * count / t_batch, 1),
-        "identical_results": one_best == batch_best if one_at_a_time else None,
         "n_gpus": 1, "higher_is_better": True, "dtype": "int32", "data": "synthetic",
         "config": {"workload": f"{count} instances, n log-uniform in [20, 500] (min {min(ns)}, "
                                f"max {max(ns)}), facade/bridge by seed, swarm 256, "
@@ -239,14 +248,16 @@ def bench_batch(count: int, generations: int, cpu_seconds: float = 0.0, one_at_a
 
 
 def bench_serve(count: int, rate: float, warmup: int, budget_mb: int, one_at_a_time: bool = False,
-                sites: int = 100):
+                sites: int = 100, plain: bool = False):
     """Served re-planning: Poisson arrivals at `rate`/s over `sites` sites (n
     log-uniform in [50, 800], facades and bridges), swarm 512, 300 generations
     per request, one in five re-plans after a moved obstacle; sites keep their
     distance matrix and swarm resident on the device under the memory budget
     (least recently used evicted), requests admitted first come, first served
     and run as batches. With `one_at_a_time`, every admitted batch holds one
-    request (the baseline)."""
+    request; with `plain` as well, each request runs on the plain
+    single-instance path (dpso_init_nn, dpso_run) instead of a batch of one
+    (the baseline)."""
     import torch
     from paper_1706_04399_amd import serve
 
@@ -256,14 +267,16 @@ def bench_serve(count: int, rate: float, warmup: int, budget_mb: int, one_at_a_t
     warm.solve([serve.Request(0, 0.0, reqs[0].scene, dict(reqs[0].params, max_generations=5))])
     del warm
     torch.cuda.synchronize()
-    ex = serve.GpuExecutor(budget)
-    sched = serve.Scheduler(budget, ex.footprint, max_batch=1 if one_at_a_time else 1024)
+    ex = serve.GpuExecutor(budget, single=plain)
+    sched = serve.Scheduler(budget, ex.footprint, max_batch=1 if one_at_a_time or plain else 1024)
     t0 = time.perf_counter()
     recs = serve.serve(reqs, ex, sched)
     wall = time.perf_counter() - t0
     s = serve.summary(recs, warmup=warmup, scheduler=sched)
     return {
-        "metric": "served re-planning p99 latency" + (" (one request per batch)" if one_at_a_time else ""),
+        "metric": "served re-planning p99 latency" + (" (one request at a time, single-instance path)"
+                                                      if plain else " (one request per batch)"
+                                                      if one_at_a_time else ""),
         "value": round(s["p99_ms"], 2), "unit": "ms", "p50_ms": round(s["p50_ms"], 2),
         "mean_ms": round(s["mean_ms"], 2), "max_ms": round(s["max_ms"], 2),
         "solves_per_s": round(s["solves_per_s"], 2), "batches": s["batches"],
@@ -275,7 +288,8 @@ def bench_serve(count: int, rate: float, warmup: int, budget_mb: int, one_at_a_t
                                f"[50, 800], swarm 512, 300 generations per request, 20 % of re-plans "
                                f"after a moved obstacle, {count} requests (first {warmup} not "
                                f"counted), budget {budget_mb} MiB",
-                   "server": "one request per batch" if one_at_a_time else "batched, FCFS admission, "
+                   "server": "one request at a time on the single-instance path" if plain else
+                             "one request per batch" if one_at_a_time else "batched, FCFS admission, "
                              "resident sites"},
     }
 
@@ -433,21 +447,20 @@ def main():
     ap.add_argument("--batch", type=int, default=0,
                     help="run the batched workload with this many instances instead")
     ap.add_argument("--batch-generations", type=int, default=500)
-    ap.add_argument("--plain-leg", action="store_true",
-                    help="with --batch: also solve the instances one at a time on the "
-                         "single-instance path (refused, see PLAIN_LEGS_REFUSED)")
+    ap.add_argument("--no-plain-leg", action="store_true",
+                    help="with --batch: skip solving the instances one at a time on the "
+                         "single-instance path")
     ap.add_argument("--serve", type=int, default=0,
                     help="serve this many re-planning requests instead")
     ap.add_argument("--rate", type=float, default=50.0)
     ap.add_argument("--serve-warmup", type=int, default=200)
     ap.add_argument("--budget-mb", type=int, default=2048)
     ap.add_argument("--plain", action="store_true",
-                    help="serve one request at a time on the single-instance path (refused, "
-                         "see PLAIN_LEGS_REFUSED)")
+                    help="with --serve: one request at a time on the single-instance path")
     ap.add_argument("--one-per-batch", action="store_true",
                     help="with --serve: admit one request per batch (the baseline)")
-    ap.add_argument("--no-one-at-a-time", action="store_true",
-                    help="with --batch: skip the one-instance-per-call leg")
+    ap.add_argument("--one-per-call", action="store_true",
+                    help="with --batch: also solve the instances one per call of the batched path")
     ap.add_argument("--ablation", type=int, default=0,
                     help="run the augmentation ablation with this many trials per variant instead")
     ap.add_argument("--ablation-generations", type=int, default=200)
@@ -459,13 +472,10 @@ def main():
               "on one GPU; see the multi-GPU design notes)", file=sys.stderr)
         sys.exit(2)
 
-    if (args.batch and args.plain_leg) or (args.serve and args.plain):
-        print(PLAIN_LEGS_REFUSED, file=sys.stderr)
-        sys.exit(2)
     if args.batch:
         print(json.dumps(bench_batch(args.batch, args.batch_generations,
                                      0.0 if args.no_cpu else args.cpu_seconds,
-                                     not args.no_one_at_a_time)), flush=True)
+                                     not args.no_plain_leg, args.one_per_call)), flush=True)
         return
     if args.ablation:
         print(json.dumps(bench_ablation(args.ablation, args.ablation_generations)), flush=True)
@@ -475,7 +485,7 @@ def main():
         return
     if args.serve:
         print(json.dumps(bench_serve(args.serve, args.rate, min(args.serve_warmup, args.serve // 4),
-                                     args.budget_mb, args.one_per_batch)), flush=True)
+                                     args.budget_mb, args.one_per_batch, plain=args.plain)), flush=True)
         return
 
     import torch

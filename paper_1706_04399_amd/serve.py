@@ -251,11 +251,13 @@ class _Site:
 
 
 class GpuExecutor:
-    """Runs admitted batches with the batched C ABI. Sites keep their distance
-    matrix and swarm state in device memory until evicted; distance matrices
-    are built with the builder's static workspace (no allocation)."""
+    """Runs admitted batches with the batched C ABI (or, with `single`, each
+    request on the plain single-instance path: dpso_init_nn, dpso_run). Sites
+    keep their distance matrix and swarm state in device memory until
+    evicted; distance matrices are built with the builder's static workspace
+    (no allocation)."""
 
-    def __init__(self, budget_bytes: int, stream=None):
+    def __init__(self, budget_bytes: int, stream=None, single: bool = False):
         import torch
         from . import dpso
         self.dpso, self.torch = dpso, torch
@@ -263,6 +265,7 @@ class GpuExecutor:
         self.stream = stream if stream is not None else torch.cuda.Stream()
         self.sites = {}
         self.work = None
+        self.single = bool(single)
 
     def footprint(self, req: Request):
         return self.dpso.request_footprint(req.n, req.params, self.budget)
@@ -308,10 +311,15 @@ class GpuExecutor:
             site.t += G
             sites.append(site)
             actions.append(act)
-        if cold:
+        if self.single:
+            for site, act, req in zip(sites, actions, batch):
+                if act != "resume":
+                    d.init_nn(site.D, site.params, site.state, stream=self.stream)
+                d.run(site.D, site.params, site.state, req.run_generations, stream=self.stream)
+        elif cold:
             d.Batch([(s.D, s.params) for s in cold], stream=self.stream,
                     states=[s.state for s in cold], work=self._work(len(cold))).init()
-        for G in sorted({r.run_generations for r in batch}):
+        for G in sorted({r.run_generations for r in batch}) if not self.single else ():
             group = [s for s, r in zip(sites, batch) if r.run_generations == G]
             d.Batch([(s.D, s.params) for s in group], stream=self.stream,
                     states=[s.state for s in group], work=self._work(len(group))).run(G)

@@ -220,6 +220,26 @@ def case_batch(emu: Emu) -> bool:
     return ok
 
 
+def case_plain(emu: Emu, count: int) -> bool:
+    """The batched workload's instances (n log-uniform in [20, 500]) solved
+    one after another on the single-instance path, swarm 8, 6 generations."""
+    ok = True
+    for i in range(count):
+        sc = scenes.batch_instance(i)
+        prm = scenes.swarm_params(8, 6, seed=0, instance=i)
+        Dref = oracle.build_dist(sc)
+        D = emu.build_dist(sc)
+        st = emu.new_state(sc.n, prm)
+        emu.init_nn(D, sc.n, prm, st)
+        emu.run(D, sc.n, prm, st, 6)
+        ref = oracle.new_state(Dref, prm)
+        oracle.run(Dref, prm, ref, 6)
+        ok &= compare(f"instance {i} n={sc.n}", emu.export(st, sc.n, 8), ref)
+        emu.free(D)
+        emu.free(st[0])
+    return ok
+
+
 def case_serve(emu: Emu, count: int) -> bool:
     """The re-planning server's sequence of library calls (as serve.GpuExecutor
     makes them) on a scaled-down stream: sites with n log-uniform in [50, 800],
@@ -287,6 +307,8 @@ def main(argv):
         ok = case_quick(emu)
     elif case == "batch":
         ok = case_batch(emu)
+    elif case == "plain":
+        ok = case_plain(emu, int(argv[1]) if len(argv) > 1 else 24)
     elif case == "serve":
         ok = case_serve(emu, int(argv[1]) if len(argv) > 1 else 24)
     else:

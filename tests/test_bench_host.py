@@ -32,14 +32,3 @@ def test_more_than_one_gpu_is_refused():
 ])
 def test_exchange_kernel_name_follows_the_row_policy(n, name):
     assert bench.exchange_kernel_name(n) == name
-
-
-@pytest.mark.parametrize("args", [["--batch", "4", "--plain-leg"], ["--serve", "10", "--plain"]])
-def test_one_at_a_time_legs_on_the_single_instance_path_are_refused(args):
-    """They exit before touching the GPU, with the reason."""
-    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py")] + args,
-                       capture_output=True, text=True, timeout=300)
-    assert r.returncode == 2
-    assert "refused" in r.stderr and "single-instance" in r.stderr
-    assert r.stdout == ""
-

@@ -510,21 +510,24 @@ def test_batch_matches_oracle(dp, graph):
         assert not bad, f"instance {k} (n={D.shape[0]}): {bad}"
 
 
-def test_served_replans_match_oracle(dp):
+@pytest.mark.parametrize("single", [False, True], ids=["batched", "single_instance"])
+def test_served_replans_match_oracle(dp, single):
     """A short re-planning stream through the server (5 sites, obstacle
     changes, swarm capacity of 3 runs, a budget that holds the two largest
     sites, so that sites are evicted): every served plan equals the oracle replaying the same sequence
     of actions per site (a fresh swarm for plan / rebuild / restart on the
-    request's scene, the site's previous swarm run further for resume)."""
+    request's scene, the site's previous swarm run further for resume). The
+    server runs requests as batches, or one at a time on the single-instance
+    path."""
     import collections
     from paper_1706_04399_amd import serve
     reqs = serve.replan_requests(40, rate=400.0, seed=9, sites=5, n_lo=20, n_hi=120, swarm=32,
                                  generations=15, change_permille=300, capacity_runs=3)
     sizes = sorted({r.key: dp.request_footprint(r.n, r.params, 1 << 40)[1] for r in reqs}.values())
     budget = sizes[-1] + sizes[-2]             # the two largest sites fit together, not all five
-    ex = serve.GpuExecutor(budget_bytes=budget)
-    sched = serve.Scheduler(budget, ex.footprint)
-    note("served re-planning stream of 40 requests against the oracle")
+    ex = serve.GpuExecutor(budget_bytes=budget, single=single)
+    sched = serve.Scheduler(budget, ex.footprint, max_batch=1 if single else 1024)
+    note(f"served re-planning stream of 40 requests against the oracle, single={single}")
     recs = serve.serve(reqs, ex, sched)
     assert sorted(r.rid for r in recs) == list(range(40)) and all(r.status == 0 for r in recs)
     acts = collections.Counter(r.action for r in recs)
