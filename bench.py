@@ -6,9 +6,17 @@ every generation (w = 0.7, phi1 = phi2 = 1.5, mutation every 3 generations).
 One step is one generation of the whole swarm: move, mutation, global-best
 update, complete 2-opt sweep per particle. The metric is particle-iterations
 per second (swarm size x generations / seconds) with the distance matrix and
-swarm state resident in HBM.
+swarm state resident in HBM; the timed run (fresh swarm, W warm-up
+generations, K timed) is repeated and the median reported.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1]
+The same line carries the edge-exchange kernel's LDS roofline and HBM
+traffic, the whole step against the L2 roofline of the distance reads, the
+measured memory-path ceilings, the n = 30 and n = 200 workloads, the batched
+workload against the plain single-instance path, a served re-planning run
+and the oracle timed on the host.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--reps R] [--no-extras]
+    python bench.py --batch 256 | --serve 3000 [--plain] | --ablation 15 | --voxel 3
 """
 import argparse
 import json
@@ -444,6 +452,12 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-ceilings", action="store_true",
                     help="skip the memory-path micro-benchmarks")
+    ap.add_argument("--reps", type=int, default=5,
+                    help="repetitions of the timed run (fresh swarm each); the median is reported")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the other workloads (n=30, n=200, batched, served) in the default line")
+    ap.add_argument("--extra-serve", type=int, default=1000,
+                    help="requests of the served run in the default line")
     ap.add_argument("--batch", type=int, default=0,
                     help="run the batched workload with this many instances instead")
     ap.add_argument("--batch-generations", type=int, default=500)
@@ -496,44 +510,49 @@ def main():
     prm = dict(prm, max_generations=args.warmup + args.steps + phase_gens)
     n, S = sc.n, prm["swarm_size"]
     D = dpso.build_dist(sc)
-    state = dpso.init_nn(D, prm)
-    dpso.run(D, prm, state, args.warmup)
-    torch.cuda.synchronize()
-    info0 = dpso.get_info(state)
+    # the same run (fresh swarm, W warm-up generations, then K timed) repeated;
+    # the median repetition is reported
+    runs = []
+    for _ in range(max(1, args.reps)):
+        state = dpso.init_nn(D, prm)
+        dpso.run(D, prm, state, args.warmup)
+        torch.cuda.synchronize()
+        info0 = dpso.get_info(state)
+        start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        start.record()
+        timed = dpso.run_timed(D, prm, state, args.steps)   # events around the exchange launches only
+        end.record()
+        torch.cuda.synchronize()
+        info1 = dpso.get_info(state)
+        assert info1["generation"] - info0["generation"] == args.steps
+        runs.append((start.elapsed_time(end), timed, info1["sweeps"] - info0["sweeps"], info1, state))
+    order = sorted(range(len(runs)), key=lambda r: runs[r][0])
+    ms, timed, sweeps, info1, state = runs[order[len(runs) // 2]]
+    gens = args.steps
 
-    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    start.record()
-    timed = dpso.run_timed(D, prm, state, args.steps)   # events around the exchange launches only
-    end.record()
-    torch.cuda.synchronize()
-    ms = start.elapsed_time(end)
-    info1 = dpso.get_info(state)
-    gens = info1["generation"] - info0["generation"]
-    assert gens == args.steps, (gens, args.steps)
-
-    sweeps = info1["sweeps"] - info0["sweeps"]
     bytes_per_sweep = 4 * n * (n - 3) + 4 * n     # two gathers per exchange + edge costs
     launches = timed["exchange_launches"]
     avg_launch_s = timed["ms_exchange"] / launches / 1e3
-    achieved = sweeps / launches * bytes_per_sweep / avg_launch_s / 1e9
+    per_launch = sweeps / launches                 # sweeps in one exchange launch
+    algorithmic_GBs = per_launch * bytes_per_sweep / avg_launch_s / 1e9
+    exchanges_G = per_launch * n * (n - 3) / 2 / avg_launch_s / 1e9
     tb = hbm_traffic_per_launch()
     traffic = round(tb / avg_launch_s / 1e9, 2) if tb is not None else None
+    value = S * gens / (ms / 1e3)
 
     line = {
         "metric": "particle-iters/s at n=1000",
-        "value": round(S * gens / (ms / 1e3), 1),
+        "value": round(value, 1),
         "unit": "particle-iters/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms / args.steps, 4),
+        "ms_per_step_repetitions": [round(r[0] / args.steps, 4) for r in runs],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "int32", "data": "synthetic",
         "config": {"workload": "facade n=1000, 20 boxes, swarm 4096, edge exchange every "
                                "generation", "n": n, "swarm": S, "generations": args.steps,
-                   "parallelism": "none (1 GPU)"},
-        "roofline": {"bound": "hbm", "kernel": exchange_kernel_name(n),
-                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic},
+                   "repetitions": len(runs), "parallelism": "none (1 GPU)"},
         "exchange_ms_per_launch": round(avg_launch_s * 1e3, 4),
         "best_cost_mm": info1["best_cost"],
     }
@@ -542,6 +561,7 @@ def main():
     phases = dpso.run_profiled(D, prm, state, phase_gens)
     line["phases_ms_per_generation"] = {k[3:]: round(v / phase_gens, 4) for k, v in phases.items()
                                         if k.startswith("ms_")}
+    del runs
     # the distance builder, timed on its own after the timed region: median of 5
     build_ms = []
     for _ in range(6):
@@ -552,10 +572,29 @@ def main():
         b.synchronize()
         build_ms.append(a.elapsed_time(b))
     line["build_dist_ms_median5"] = round(sorted(build_ms[1:])[2], 3)
-    if not args.no_ceilings:
-        c = measure_ceilings()
+    c = measure_ceilings() if not args.no_ceilings else None
+    packed = 8 <= n <= 1024 and (n > 256 or n % 4 != 0)
+    # The dominant kernel (the edge exchange) is bound by its LDS: every
+    # exchange evaluation is one random LDS read of a staged row (the matrix
+    # itself is served from L2 and its HBM traffic is small, see `traffic`).
+    # achieved: exchange evaluations per second of its launches = random LDS
+    # reads per second; peak: the measured random LDS read rate at the same
+    # occupancy and width (2-byte reads for 16-bit rows).
+    peak = None
+    if c is not None:
+        peak = c["lds_random_read16_G_per_s"] if packed else c["lds_random_read_G_per_s"]
+    line["roofline"] = {
+        "bound": "lds", "kernel": exchange_kernel_name(n),
+        "achieved": round(exchanges_G, 1), "peak": peak, "unit": "G LDS reads/s",
+        "frac": round(exchanges_G / peak, 4) if peak else None, "traffic": traffic,
+        "traffic_unit": "GB/s of HBM (counters)",
+        "algorithmic_GBs": round(algorithmic_GBs, 1), "hbm_peak_GBs": HBM_PEAK_GBS,
+    }
+    counters = exchange_counters()
+    if counters is not None:
+        line["roofline"]["counters"] = counters
+    if c is not None:
         bpi = 4 * n * (n - 1)                       # algorithmic bytes per particle-iteration
-        per_launch = sweeps / launches              # sweeps in one exchange launch
         # time the exchange kernel cannot go below at the measured rates: one
         # random LDS read per exchange, and one staged row per row of the sweep
         # (n - 1 rows). Rows that go straight from memory into LDS (16-bit rows
@@ -564,7 +603,6 @@ def main():
         # serves both, so their sum is given too). Rows staged through
         # registers take LDS store time as well: the sum.
         mb = next(m for m in (1, 2, 4, 8, 16) if n <= 64 * m)
-        packed = 8 <= n <= 1024 and (n > 256 or n % 4 != 0)
         if packed:
             gather_s = per_launch * n * (n - 3) / 2 / (c["lds_random_read16_G_per_s"] * 1e9)
             row_bytes = 1024 * ((mb + 7) // 8)      # staged per row (whole 1 KB chunks)
@@ -579,8 +617,9 @@ def main():
             gather_s = per_launch * n * (n - 3) / 2 / (c["lds_random_read_G_per_s"] * 1e9)
             stage_s = per_launch * (n - 2) * 4 * n / (c["lds_row_write_GBs"] * 1e9)
             bound_s = gather_s + stage_s
+        l2_bound = c["l2_stream_GBs"] * 1e9 / bpi
         c.update({
-            "l2_stream_bound_piters_per_s": round(c["l2_stream_GBs"] * 1e9 / bpi, 1),
+            "l2_stream_bound_piters_per_s": round(l2_bound, 1),
             "l2_gather_bound_piters_per_s": round(c["l2_random_gather_GBs"] * 1e9 / bpi, 1),
             "exchange_gather_us": round(gather_s * 1e6, 1),
             "exchange_staging_us": round(stage_s * 1e6, 1),
@@ -593,9 +632,82 @@ def main():
             "valu_bound_piters_per_s": round(VALU_LANE_OPS_PER_S / (8 * n * (n - 3) / 2), 1),
         })
         line["ceilings"] = c
+        # the whole step against the L2 roofline of the distance reads (the
+        # stream rate over 4 n (n - 1) int32 bytes per particle-iteration)
+        line["l2_roofline"] = {"bound_piters_per_s": round(l2_bound, 1), "frac": round(value / l2_bound, 4)}
+    if not args.no_extras:
+        line["workloads"] = {"facade30": small_workload(1, 5), "bridge200": small_workload(2, 5)}
+        line["batched"] = compact_batch(bench_batch(256, 500))
+        line["served"] = compact_serve(bench_serve(args.extra_serve, 50.0, args.extra_serve // 5, 2048))
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(line), flush=True)
+
+
+def small_workload(k: int, reps: int):
+    """Particle-iterations/s of a whole single-instance run of workload k
+    (1: facade n=30, swarm 64, 200 generations; 2: bridge girder n=200, swarm
+    1024, 1000 generations; exchange on stall), init excluded, median of
+    `reps` fresh runs, with the oracle-equal best cost."""
+    import torch
+    from paper_1706_04399_amd import dpso, scenes
+    sc, prm = scenes.workload(k)
+    D = dpso.build_dist(sc)
+    G, S = prm["max_generations"], prm["swarm_size"]
+    ms, best = [], None
+    for _ in range(reps + 1):
+        st = dpso.init_nn(D, prm)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record()
+        dpso.run(D, prm, st, G)
+        b.record()
+        b.synchronize()
+        ms.append(a.elapsed_time(b))
+        best = dpso.get_best(st)[1]
+    m = sorted(ms[1:])[len(ms[1:]) // 2]
+    return {"particle_iters_per_s": round(S * G / (m / 1e3), 1), "ms_per_run": round(m, 3),
+            "n": sc.n, "swarm": S, "generations": G, "best_cost_mm": best,
+            "note": "median of %d runs after one warm-up, init excluded" % reps}
+
+
+def compact_batch(r: dict) -> dict:
+    keys = ("value", "unit", "seconds_batched", "plain_value", "speedup_vs_plain", "identical_results_plain",
+            "particle_iters_per_s")
+    return {k: r[k] for k in keys if k in r} | {"workload": r["config"]["workload"]}
+
+
+def compact_serve(r: dict) -> dict:
+    keys = ("p50_ms", "value", "solves_per_s", "mean_batch", "state_hit_rate", "dist_hit_rate", "evictions",
+            "rejected")
+    out = {k: r[k] for k in keys}
+    out["p99_ms"] = out.pop("value")
+    out["workload"] = r["config"]["workload"]
+    return out
+
+
+def exchange_counters():
+    """VALU busy, LDS and L2 figures of the edge-exchange kernel from the
+    committed rocprofv3 counter summary, or None if the kernel source changed
+    since it was taken."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "counters_facade1000.md")
+    try:
+        text = open(path).read()
+        src = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    except OSError:
+        return None
+    h = re.search(r"source_sha256_16:\s*([0-9a-f]{16})", text)
+    if not h or h.group(1) != src:
+        return None
+    out = {}
+    for key in ("valu_busy_pct", "lds_active_pct", "lds_bank_conflict_pct", "l2_read_GBs", "l2_hit_pct"):
+        m = re.search(key + r":\s*([0-9.]+)", text)
+        if m:
+            out[key] = float(m.group(1))
+    out["source"] = "profiles/counters_facade1000.md"
+    return out
 
 
 if __name__ == "__main__":
