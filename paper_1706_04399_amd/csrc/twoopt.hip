@@ -212,21 +212,91 @@ __device__ inline void dma_row(const int32_t *src, int n, lds_int *dst)
     compiler_fence();
 }
 
-// A padded row of hs uint16 (hs a multiple of 8) into an LDS buffer: chunk k
-// of 64 x 16 bytes lands at byte 1024 k of dst, chunk indices clamped to the
-// row.
+// A padded row of hs uint16 (hs a multiple of 8) into an LDS buffer: the
+// buffer's slot 64 k + lane (16 bytes at byte 1024 k + 16 lane of dst) takes
+// chunk src_chunk[k] of the row (chunk c: bytes 16 c .. 16 c + 15, labels
+// 8 c .. 8 c + 7), so a chunk can go to any slot.
 template <int R>
-__device__ inline void dma_half(const uint16_t *src, int hs, lds_int *dst)
+__device__ inline void dma_half(const uint16_t *src, const int *src_chunk, lds_int *dst)
 {
     typedef __attribute__((address_space(1))) const void GV;
     typedef __attribute__((address_space(3))) void LV;
-    const int lane = threadIdx.x, q = (hs >> 3) - 1;
     compiler_fence();
 #pragma unroll
     for (int k = 0; k < R; ++k)
-        __builtin_amdgcn_global_load_lds((GV *)(reinterpret_cast<const char *>(src) + 16 * min(lane + 64 * k, q)),
+        __builtin_amdgcn_global_load_lds((GV *)(reinterpret_cast<const char *>(src) + 16 * src_chunk[k]),
                                          (LV *)(dst + 256 * k), 16, 0, 0);
     compiler_fence();
+}
+
+// Chunk placement for the 16-bit rows of one sweep. A row buffer's 16-byte
+// slot s covers LDS banks 4 (s mod 8) .. 4 (s mod 8) + 3 (32 banks of 4 bytes,
+// a wave's gather served 32 lanes at a time), so the bank of label y is
+// 4 g + (y mod 8) / 2 with g the group (slot mod 8) of its chunk y / 8. The
+// half-wave of lanes 32 h .. 32 h + 31 of column block m gathers, in every
+// row of the sweep where that block is active, the labels x_c+1 of its 32
+// columns c, a fixed set for the whole sweep; it takes as many cycles as the
+// most distinct dwords any bank holds. Chunks are placed one after another
+// into the group that raises the fewest half-waves' maximum load, weighted by
+// the rows in which the half-wave gathers; 8 RH slots per group. Returns each
+// chunk's slot (slot_of, LDS) and, per lane, the chunk each of its row loads
+// fetches (src_chunk); `scratch` holds 328 MB + 256 bytes. Only the
+// layout of the staged rows changes, not what is read: results are the same
+// for every placement.
+template <int MB>
+__device__ __forceinline__ void place_chunks(const uint16_t *tour, int n, int nch, unsigned char *scratch,
+                                             const unsigned char *&slot_of, int *src_chunk)
+{
+    constexpr int RH = (MB + 7) / 8, NHW = 2 * MB, CAP = 8 * RH;
+    const int lane = threadIdx.x;
+    unsigned char *hwpos = scratch;                                             // [64 MB]
+    uint32_t *load = reinterpret_cast<uint32_t *>(scratch + 64 * MB);           // [NHW][32]
+    uint32_t *mx = load + NHW * 32;                                             // [NHW]
+    unsigned char *slot = reinterpret_cast<unsigned char *>(mx + NHW);          // [128]
+    unsigned char *chunk = slot + 128;                                          // [128]
+    for (int k = lane; k < NHW * 32; k += 64) load[k] = 0u;
+    if (lane < NHW) mx[lane] = 0u;
+    for (int p = lane; p < n; p += 64) {
+        const int c = p == 0 ? n - 1 : p - 1;  // the column whose gather reads tour[p]
+        hwpos[tour[p]] = (unsigned char)(c >> 5);
+    }
+    compiler_fence();
+    const int g = lane >> 3, r = lane & 7;
+    int cnt = 0;  // chunks placed in group g (the same in g's 8 lanes)
+    for (int q = 0; q < nch; ++q) {
+        const int y = 8 * q + r;
+        const int hw = y < n ? int(hwpos[y]) : -1 - lane;
+        const int phw = __shfl_xor(hw, 1, 64);
+        // y and its dword partner y ^ 1 read in one half-wave count once
+        const bool live = y < n && !((r & 1) && phw == hw);
+        const int cell = hw * 32 + 4 * g + (r >> 1);
+        const uint32_t ld = live ? load[cell] : 0u;
+        const uint32_t top = live ? mx[hw] : 1u;
+        int cost = live && ld == top ? min(64 * (hw >> 1) + 62, n - 2) : 0;
+        cost += __shfl_xor(cost, 1, 64);
+        cost += __shfl_xor(cost, 2, 64);
+        cost += __shfl_xor(cost, 4, 64);
+        int key = cnt < CAP ? cost * 8 + g : 0x7fffffff;
+        key = min(key, __shfl_xor(key, 8, 64));
+        key = min(key, __shfl_xor(key, 16, 64));
+        key = min(key, __shfl_xor(key, 32, 64));
+        const int gs = __builtin_amdgcn_readfirstlane(key & 7);
+        if (g == gs && live) {
+            load[cell] = ld + 1u;
+            atomicMax(&mx[hw], ld + 1u);
+        }
+        const int placed = __builtin_amdgcn_readlane(cnt, 8 * gs);
+        if (lane == 0) slot[q] = (unsigned char)(gs + 8 * placed);
+        cnt += g == gs;
+    }
+    compiler_fence();
+    for (int s = lane; s < 64 * RH; s += 64) chunk[s] = 0;
+    compiler_fence();
+    for (int q = lane; q < nch; q += 64) chunk[slot[q]] = (unsigned char)q;
+    compiler_fence();
+#pragma unroll
+    for (int k = 0; k < RH; ++k) src_chunk[k] = chunk[64 * k + lane];
+    slot_of = slot;
 }
 
 // Row buffers: two per wave, each BS ints. Rows that do not start on 16
@@ -312,8 +382,10 @@ struct SweepState {
     int g[MB];     // gathers of the previous row
     RowPipe<MB, VEC4> pipe[kPrefetch];  // rows in flight (alternating by row parity)
     int best, best_i;
-    // packed rows: the lane's three smallest keys 1024 A + i (k1 <= k2 <= k3)
+    // packed rows: the lane's three smallest keys 1024 A + i (k1 <= k2 <= k3),
+    // and the chunk each of the lane's row loads fetches
     int k1, k2, k3;
+    int src_chunk[(MB + 7) / 8];
 
     __device__ inline int off(int m) const
     {
@@ -368,14 +440,12 @@ __device__ __forceinline__ void sweep_row(SweepState<MB, VEC4> &S, const int32_t
         const int ne_lo = __builtin_amdgcn_readlane(S.ne[MP], i & 63);
         const int ne_hi = __builtin_amdgcn_readlane(S.ne[M0], i & 63);
         ei = -((M0 > 0 && (i >> 6) < M0) ? ne_lo : ne_hi);
-        const int of_lo = __builtin_amdgcn_readlane(S.off(MP), (i + 1) & 63);
-        const int of_hi = __builtin_amdgcn_readlane(S.off(M0), (i + 1) & 63);
-        const int label = ((M0 > 0 && ((i + 1) >> 6) < M0) ? of_lo : of_hi) >> 1;  // x_i+2
+        const int label = tour[i + 2];  // x_i+2 (its offset no longer encodes it)
         wait_vmem();
         wait_lds();
         compiler_fence();
         const int hs = packed_stride(n);
-        if (i + 4 <= n) dma_half<WaveCfg<MB, VEC4>::RH>(H + size_t(label) * hs, hs, lbufs + (1 - BI) * ST);
+        if (i + 4 <= n) dma_half<WaveCfg<MB, VEC4>::RH>(H + size_t(label) * hs, S.src_chunk, lbufs + (1 - BI) * ST);
     } else if constexpr (kDma && VEC4) {
         // e_i = D[x_i][x_i+1] and the label x_i+2 come from the registers of
         // the lanes owning columns i and i + 1 (in this phase, blocks M0 - 1
@@ -482,12 +552,18 @@ __device__ __forceinline__ void twoopt_wave_body(const Inst &I, int p)
         ++sweeps;
         if (n < 4) break;
         SweepState<MB, VEC4> S;
+        const unsigned char *slot_of = nullptr;
+        if constexpr (HALF) {
+            // the row buffers are free until the first row load below
+            wait_lds();
+            place_chunks<MB>(tour, n, hs / 8, reinterpret_cast<unsigned char *>(bufs), slot_of, S.src_chunk);
+        }
 #pragma unroll
         for (int m = 0; m < MB; ++m) {
             const int c = lane + 64 * m;
             if (c < n) {
                 const int a = tour[c], b = tour[c + 1 < n ? c + 1 : 0];
-                S.set_off(m, HALF ? 2 * b : 4 * b);
+                S.set_off(m, HALF ? 16 * int(slot_of[b >> 3]) + 2 * (b & 7) : 4 * b);
                 S.ne[m] = HALF ? -int(H[size_t(a) * hs + b]) : -D[size_t(a) * n + b];
             } else {
                 S.set_off(m, 0);
@@ -496,13 +572,13 @@ __device__ __forceinline__ void twoopt_wave_body(const Inst &I, int p)
         }
         // g <- D[x_0][x_c+1]: the first term of row 0, one column to the right
         if constexpr (HALF) {
-            wait_lds();
-            dma_half<WaveCfg<MB, VEC4>::RH>(H + size_t(tour[0]) * hs, hs, lbufs + ST);
+            wait_lds();  // the placement's reads of the buffers are done
+            dma_half<WaveCfg<MB, VEC4>::RH>(H + size_t(tour[0]) * hs, S.src_chunk, lbufs + ST);
             wait_vmem();
             compiler_fence();
 #pragma unroll
             for (int m = 0; m < MB; ++m) S.g[m] = lds_half(bufs + ST, S.off(m));
-            dma_half<WaveCfg<MB, VEC4>::RH>(H + size_t(tour[1]) * hs, hs, lbufs);
+            dma_half<WaveCfg<MB, VEC4>::RH>(H + size_t(tour[1]) * hs, S.src_chunk, lbufs);
         } else if constexpr (kDma && VEC4) {
             wait_lds();  // earlier reads of both buffers are done
             dma_row<WaveCfg<MB, VEC4>::RV>(D + size_t(tour[0]) * n, n, lbufs + ST);

@@ -159,6 +159,7 @@ void resolve_wave(std::vector<Lane> &lanes, int w0, int w1)
             break;
         }
         case kRor1: L.result = value_of((l + 63) & 63, "row rotate"); break;
+        case kReadFirst: L.result = lanes[at[0]].a; break;
         case kInvBallot: {
             for (int j : at)
                 if (lanes[j].a != L.a) fail("inverse ballot of a mask that differs across lanes");

@@ -56,7 +56,7 @@ inline int4 make_int4(int a, int b, int c, int d) { return int4{a, b, c, d}; }
 namespace emu {
 
 enum Wait { kRun = 0, kWave = 1, kBarrier = 2, kDone = 3 };
-enum WaveOp { kSync = 0, kBallot, kShflXor, kShflIdx, kShflUp, kReadlane, kRor1, kInvBallot };
+enum WaveOp { kSync = 0, kBallot, kShflXor, kShflIdx, kShflUp, kReadlane, kRor1, kInvBallot, kReadFirst };
 
 struct Lane {
     dim3 tid;
@@ -168,6 +168,10 @@ inline T __shfl_up(T v, unsigned delta, int width = 64)
 inline int emu_amdgcn_readlane(int v, int lane)
 {
     return ::emu::from_bits<int>(::emu::wave_op(::emu::kReadlane, ::emu::bits(v), uint64_t(lane)));
+}
+inline int emu_amdgcn_readfirstlane(int v)
+{
+    return ::emu::from_bits<int>(::emu::wave_op(::emu::kReadFirst, ::emu::bits(v)));
 }
 inline int emu_amdgcn_mov_dpp(int v, int ctrl, int, int, bool)
 {
