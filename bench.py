@@ -34,15 +34,41 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_facade1000.md")
 KERNEL_SRC = os.path.join(ROOT, "paper_1706_04399_amd", "csrc", "twoopt.hip")
 
 
-def exchange_kernel_name(n: int) -> str:
-    # <columns per lane / 64, rows go straight into LDS, 16-bit rows>; 16-bit
-    # rows are padded to 16 bytes, so they always go straight into LDS
-    for mb in (1, 2, 4, 8, 16):
-        if n <= 64 * mb:
-            packed = 8 <= n and (n > 256 or n % 4 != 0)
-            direct = packed or n % 4 == 0
-            return f"k_2opt_wave<{mb}, {'true' if direct else 'false'}, {'true' if packed else 'false'}>"
-    return "k_2opt_rows"
+def exchange_kernel_name(n: int, rows: int) -> str:
+    """The edge-exchange kernel an instance of n runs with the row form
+    `rows` (1: 16-bit, 2: int32, 3: one workgroup per particle):
+    <columns per lane / 64, rows go straight into LDS, 16-bit rows>; 16-bit
+    rows are padded to 16 bytes, so they always go straight into LDS."""
+    if rows == 3 or n > 1024:
+        return "k_2opt_rows"
+    mb = next(m for m in (1, 2, 4, 8, 16) if n <= 64 * m)
+    packed = rows == 1
+    direct = packed or n % 4 == 0
+    return f"k_2opt_wave<{mb}, {'true' if direct else 'false'}, {'true' if packed else 'false'}>"
+
+
+def setup_tuning(run_tuner: bool) -> dict:
+    """Fills the library's tuning table: the saved picks for this device if
+    there are any, else the autotuner's run over the default buckets (saved
+    for later runs). Outside every timed region."""
+    from paper_1706_04399_amd import tune
+    if not run_tuner:
+        return {"source": "built-in defaults"}
+    t0 = time.time()
+    loaded = tune.load()
+    if loaded:
+        return {"source": "saved picks", "entries": loaded, "path": tune.cache_path(),
+                "seconds": round(time.time() - t0, 2)}
+    table = tune.tune()
+    try:
+        path = tune.save(table)
+    except OSError:
+        path = None
+    return {"source": "autotuner", "entries": len(table["entries"]), "seconds": table["seconds"],
+            "path": path, "picks": [{"n": e["n"], "particles": e["particles"], **e["chosen"],
+                                     "candidates_ms": {f"{r['move_threads']}/{r['exchange_rows']}": round(r["ms"], 3)
+                                                       for r in e["results"]}}
+                                    for e in table["entries"]]}
 
 
 def hbm_traffic_per_launch():
@@ -480,12 +506,22 @@ def main():
     ap.add_argument("--ablation-generations", type=int, default=200)
     ap.add_argument("--voxel", type=int, default=0,
                     help="time the voxel-grid planner (this many builds per case) instead")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="use the library's built-in launch configuration instead of the autotuner's picks")
+    ap.add_argument("--batch-order", type=int, default=0,
+                    help="order of the batched launches: 0 default, 1 index, 2 longest first, 3 XCD groups")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (each swarm runs "
               "on one GPU; see the multi-GPU design notes)", file=sys.stderr)
         sys.exit(2)
 
+    tuning = None
+    if not (args.ablation or args.voxel):
+        from paper_1706_04399_amd import dpso
+        tuning = setup_tuning(not args.no_tune)
+        dpso.batch_order_set(args.batch_order)
+        tuning["batch_order"] = dpso.batch_order_get()
     if args.batch:
         print(json.dumps(bench_batch(args.batch, args.batch_generations,
                                      0.0 if args.no_cpu else args.cpu_seconds,
@@ -510,6 +546,7 @@ def main():
     prm = dict(prm, max_generations=args.warmup + args.steps + phase_gens)
     n, S = sc.n, prm["swarm_size"]
     D = dpso.build_dist(sc)
+    config = dpso.tuning_get(n, S)
     # the same run (fresh swarm, W warm-up generations, then K timed) repeated;
     # the median repetition is reported
     runs = []
@@ -555,6 +592,8 @@ def main():
                    "repetitions": len(runs), "parallelism": "none (1 GPU)"},
         "exchange_ms_per_launch": round(avg_launch_s * 1e3, 4),
         "best_cost_mm": info1["best_cost"],
+        "launch_config": config,
+        "tuning": tuning,
     }
     # device time per generation of each phase, from a profiled run after the
     # timed region (its events between phases add a little time of their own)
@@ -573,7 +612,7 @@ def main():
         build_ms.append(a.elapsed_time(b))
     line["build_dist_ms_median5"] = round(sorted(build_ms[1:])[2], 3)
     c = measure_ceilings() if not args.no_ceilings else None
-    packed = 8 <= n <= 1024 and (n > 256 or n % 4 != 0)
+    packed = config["exchange_rows"] == dpso.ROWS_U16
     # The dominant kernel (the edge exchange) is bound by its LDS: every
     # exchange evaluation is one random LDS read of a staged row (the matrix
     # itself is served from L2 and its HBM traffic is small, see `traffic`).
@@ -584,7 +623,7 @@ def main():
     if c is not None:
         peak = c["lds_random_read16_G_per_s"] if packed else c["lds_random_read_G_per_s"]
     line["roofline"] = {
-        "bound": "lds", "kernel": exchange_kernel_name(n),
+        "bound": "lds", "kernel": exchange_kernel_name(n, config["exchange_rows"]),
         "achieved": round(exchanges_G, 1), "peak": peak, "unit": "G LDS reads/s",
         "frac": round(exchanges_G / peak, 4) if peak else None, "traffic": traffic,
         "traffic_unit": "GB/s of HBM (counters)",

@@ -150,9 +150,9 @@ dpso_status dpso_validate_params(const dpso_params *params, int32_t n);
  * swarm_size and max_generations generations; 0 if the sizes are out of
  * range. The buffer holds every particle's tour, personal best and
  * velocity, costs, the global best, the cost trace and the scratch space
- * used by the generation loop, and, for 8 <= n <= 1024 except multiples of 4
- * up to 256, the 16-bit copy of D with rows padded to a multiple of 8 entries
- * (2 n ceil8(n) bytes) that the edge exchange stages, rewritten by every run:
+ * used by the generation loop, and, for 8 <= n <= 1024, the 16-bit copy of D
+ * with rows padded to a multiple of 8 entries (2 n ceil8(n) bytes) that the
+ * edge exchange stages (DPSO_ROWS_U16), rewritten by every run that uses it:
  * dpso_run allocates nothing. */
 size_t dpso_state_bytes(int32_t n, int32_t swarm_size, int32_t max_generations);
 
@@ -380,6 +380,89 @@ dpso_status dpso_export_state(const void *d_state, int32_t n, int32_t swarm_size
  * `stream`. */
 dpso_status dpso_import_state(void *d_state, size_t state_bytes, int32_t n, int32_t swarm_size,
                               const dpso_host_state *in, void *stream);
+
+/* ------------------------------------------------------------- tuning
+ * How the generation loop is laid out on the GPU, per instance: threads per
+ * particle in the move, and how the edge exchange stages rows of D. Every
+ * configuration computes the same result bit for bit; only the speed
+ * differs. The library keeps one table per device, keyed by the bucket of n
+ * (n in (2^(b-1), 2^b], b = 1 .. 12) and the bucket of the particles that run
+ * together (the swarm of a single-instance call, the batch's total particles
+ * in a batched call: <= 128, <= 512, <= 1024, <= 2048, <= 8192, more). An
+ * empty entry takes the built-in default. The table lives in process memory;
+ * the Python package saves and reloads it per device. */
+#define DPSO_ROWS_AUTO 0  /* the default for n                                  */
+#define DPSO_ROWS_U16 1   /* one wavefront per particle, rows of the 16-bit copy
+                             of D (8 <= n <= 1024), candidates checked exactly  */
+#define DPSO_ROWS_I32 2   /* one wavefront per particle, int32 rows (n <= 1024)  */
+#define DPSO_ROWS_BLOCK 3 /* one workgroup per particle, int32 rows (any n)     */
+
+typedef struct {
+    int32_t move_threads;  /* 64, 128 or 256 threads per particle (0: default);
+                              n must be at most 16 * move_threads               */
+    int32_t exchange_rows; /* DPSO_ROWS_*; a form that does not serve an n of the
+                              bucket (U16 below 8) falls back to the default    */
+} dpso_tuning;
+
+/* The configuration the library uses for an instance of n viewpoints among
+ * `particles` particles launched together, on the current device. The
+ * exchange form is reported as resolved for n (never DPSO_ROWS_AUTO). Host
+ * only. */
+dpso_status dpso_tuning_get(int32_t n, int32_t particles, dpso_tuning *out);
+
+/* Sets the table entry of the bucket holding (n, particles) on the current
+ * device; `t` NULL clears it. DPSO_E_RANGE if move_threads cannot serve the
+ * bucket's largest n, or an int32 or 16-bit wavefront form is asked for
+ * above n = 1024; DPSO_E_INVAL for other values. Calls racing with runs on
+ * other threads see either entry. Host only. */
+dpso_status dpso_tuning_set(int32_t n, int32_t particles, const dpso_tuning *t);
+
+/* Clears the whole table of the current device (and restores the default
+ * batch order). Host only. */
+dpso_status dpso_tuning_reset(void);
+
+/* Order of the particles in each batched move and edge-exchange launch, per
+ * device; results are the same in every order. */
+#define DPSO_ORDER_DEFAULT 0 /* the library's choice (DPSO_ORDER_LPT)            */
+#define DPSO_ORDER_INDEX 1   /* instances in the order of the batch               */
+#define DPSO_ORDER_LPT 2     /* most work first (swarm x n^2 in the exchange,
+                                swarm x n in the move)                             */
+#define DPSO_ORDER_XCD 3     /* LPT order dealt to eight groups of balanced work,
+                                one per XCD (workgroups go to the XCDs in turn), so
+                                an instance's particles share one L2; falls back to
+                                LPT when the groups cannot be balanced            */
+
+/* Sets the batch order of the current device. DPSO_E_INVAL for an unknown
+ * value. Host only. */
+dpso_status dpso_batch_order_set(int32_t order);
+
+/* The batch order in use on the current device (never DPSO_ORDER_DEFAULT).
+ * Host only. */
+int32_t dpso_batch_order_get(void);
+
+typedef struct {
+    dpso_tuning config;
+    float ms;         /* best of two timed runs of `generations` generations  */
+    uint64_t digest;  /* FNV-1a of the swarm after the run (tours, personal
+                         bests, velocities, costs, global best, trace, counters) */
+} dpso_tune_result;
+
+/* Autotuner: times `generations` generations of the given swarm under each
+ * candidate configuration (threads per particle in the move, then the
+ * exchange's row form with the fastest move; the two phases are separate
+ * kernels, so their times add) and records the fastest in the table entry of
+ * (n, swarm_size). Every candidate starts from the same snapshot of the state
+ * (kept in d_scratch, at least state_bytes) and the state is restored at the
+ * end, so the call leaves d_state as it found it. The candidates' digests
+ * must agree: a disagreement returns DPSO_E_STATE and records nothing.
+ * results (nullable, max_results entries) receive every timed candidate in
+ * order, *n_results their count, *chosen (nullable) the pick. The state must
+ * be initialised and at least `generations` generations short of
+ * max_generations. Synchronises `stream`. */
+dpso_status dpso_autotune(const int32_t *d_dist, int32_t n, const dpso_params *params, void *d_state,
+                          size_t state_bytes, int32_t generations, void *d_scratch, size_t scratch_bytes,
+                          dpso_tune_result *results, int32_t max_results, int32_t *n_results,
+                          dpso_tuning *chosen, void *stream);
 
 #ifdef __cplusplus
 }

@@ -11,6 +11,7 @@
 #include "dpso.h"
 #include "errors.hpp"
 #include "kernels.hpp"
+#include "tune.hpp"
 
 namespace dpso {
 
@@ -187,11 +188,23 @@ bool host_velocity_tours(const uint16_t *pairs, int len, int n, uint16_t *from, 
 }
 
 // Device workspace of a batch: the descriptors of all instances with two
-// prefix tables (per particle, per instance), and for every edge-exchange
-// class the descriptors of its members with their particle prefix.
+// prefix tables (per particle, per instance), and for every move class and
+// every edge-exchange class the descriptors of its members with their
+// particle prefix.
+constexpr int kMoveClasses = 15;  // threads per particle 64 / 128 / 256 x 1, 2, 4, 8, 16 positions each
+
+int move_class(int tpb, int ns)
+{
+    int e = 0;
+    while (e < 4 && ns > (tpb << e)) ++e;
+    return (tpb == 64 ? 0 : tpb == 128 ? 1 : 2) * 5 + e;
+}
+
+int move_class_threads(int mc) { return 64 << (mc / 5); }
+
 struct BatchLayout {
-    size_t inst, first_items, first_inst, cls_inst[dpso::kExchangeClasses],
-        cls_first[dpso::kExchangeClasses], total;
+    size_t inst, first_items, first_inst, cls_inst[dpso::kExchangeClasses], cls_first[dpso::kExchangeClasses],
+        mv_inst[kMoveClasses], mv_first[kMoveClasses], total;
 };
 
 BatchLayout batch_layout(int32_t count)
@@ -206,18 +219,86 @@ BatchLayout batch_layout(int32_t count)
         B.cls_inst[c] = take(sizeof(dpso::Inst) * size_t(count));
         B.cls_first[c] = take(4 * size_t(count + 1));
     }
+    for (int c = 0; c < kMoveClasses; ++c) {
+        B.mv_inst[c] = take(sizeof(dpso::Inst) * size_t(count));
+        B.mv_first[c] = take(4 * size_t(count + 1));
+    }
     B.total = o;
     return B;
 }
 
+// A class of a batch: its members (descriptors and particle prefix) and
+// the launch it needs.
+struct ClassPlan {
+    dpso::Batch members;
+    int total = 0, max_ns = 0, grid = 0;
+};
+
+// Launch order of a class's members. DPSO_ORDER_INDEX keeps the batch's
+// order. DPSO_ORDER_LPT puts the members with the most work (swarm times n^2
+// for the edge exchange, times n for the move) first, so the longest blocks
+// start first (longest-processing-time order). DPSO_ORDER_XCD, with 8 or more
+// members, also deals them, most work first, to eight XCD groups: each to the
+// group with the least work that has room for its particles (a group holds
+// at most ceil(total / 8) plus the largest swarm); the grouping is kept only
+// if no group's work or particle count exceeds the mean by more than an
+// eighth, else the launch is ungrouped in LPT order. Groups are listed one
+// after another, most work first within each.
+struct ClassOrder {
+    std::vector<int> order;  // member positions in launch order
+    bool groups = false;
+    int xcount[8] = {};      // particles of each XCD group
+};
+
+ClassOrder order_class(const std::vector<int64_t> &work, const std::vector<int64_t> &swarm, int mode)
+{
+    ClassOrder o;
+    const size_t m = work.size();
+    o.order.resize(m);
+    for (size_t k = 0; k < m; ++k) o.order[k] = int(k);
+    if (mode == DPSO_ORDER_INDEX || m == 0) return o;
+    std::stable_sort(o.order.begin(), o.order.end(), [&](int a, int b) { return work[size_t(a)] > work[size_t(b)]; });
+    if (mode != DPSO_ORDER_XCD || m < 8) return o;
+    int64_t total = 0, total_work = 0, biggest = 0;
+    for (size_t k = 0; k < m; ++k) {
+        total += swarm[k];
+        total_work += work[k];
+        biggest = std::max(biggest, swarm[k]);
+    }
+    const int64_t cap = (total + 7) / 8 + biggest;
+    std::vector<int> group[8];
+    int64_t load[8] = {}, parts[8] = {};
+    for (int k : o.order) {
+        int best = -1;
+        for (int x = 0; x < 8; ++x)
+            if (parts[x] + swarm[size_t(k)] <= cap && (best < 0 || load[x] < load[best])) best = x;
+        if (best < 0) return o;  // no room anywhere: ungrouped
+        group[best].push_back(k);
+        load[best] += work[size_t(k)];
+        parts[best] += swarm[size_t(k)];
+    }
+    for (int x = 0; x < 8; ++x)
+        if (8 * load[x] > 9 * total_work / 8 || 8 * parts[x] > 9 * total / 8) return o;
+    o.order.clear();
+    for (int x = 0; x < 8; ++x) {
+        o.order.insert(o.order.end(), group[x].begin(), group[x].end());
+        o.xcount[x] = int(parts[x]);
+    }
+    o.groups = true;
+    return o;
+}
+
 struct BatchPlan {
-    dpso::Batch items, instances, cls[dpso::kExchangeClasses];
-    int total = 0, max_ns = 0, cls_total[dpso::kExchangeClasses] = {}, cls_max_ns[dpso::kExchangeClasses] = {};
+    dpso::Batch items, instances;
+    ClassPlan cls[dpso::kExchangeClasses], mv[kMoveClasses];
+    int total = 0, max_ns = 0;
     bool any_mutation = false, any_exchange = false;
 };
 
 // Validates every item, writes the tables to the workspace (synchronising
-// the stream) and returns the launch plan.
+// the stream) and returns the launch plan. Each instance's move and exchange
+// classes follow the configuration of its n among all the batch's
+// particles.
 dpso_status plan_batch(const dpso_batch_item *items, int32_t count, void *d_work, size_t work_bytes,
                        hipStream_t s, BatchPlan &plan)
 {
@@ -231,7 +312,6 @@ dpso_status plan_batch(const dpso_batch_item *items, int32_t count, void *d_work
     auto first_items = reinterpret_cast<int32_t *>(host.data() + BL.first_items);
     auto first_inst = reinterpret_cast<int32_t *>(host.data() + BL.first_inst);
     int64_t total = 0;
-    int cls_count[dpso::kExchangeClasses] = {};
     for (int32_t i = 0; i < count; ++i) {
         const dpso_batch_item &it = items[i];
         dpso_status st = check_params(&it.params, it.n);
@@ -245,25 +325,28 @@ dpso_status plan_batch(const dpso_batch_item *items, int32_t count, void *d_work
         const dpso::Layout L = dpso::make_layout(it.n, it.params.swarm_size, it.params.max_generations + 1);
         if (it.state_bytes < L.total)
             return fail(DPSO_E_NOMEM, "item %d: state buffer of %zu bytes, %zu needed", i, it.state_bytes, L.total);
-        inst[i] = make_inst(it.d_dist, it.d_state, L, &it.params);
-        first_items[i] = int32_t(total);
-        first_inst[i] = i;
         total += it.params.swarm_size;
-        plan.max_ns = std::max(plan.max_ns, L.ns);
-        plan.any_mutation |= it.params.mutation_period > 0;
-        const int c = dpso::exchange_class(it.n, it.d_dist, it.params.ee_neighbourhood);
-        if (it.params.ee_trigger != DPSO_EE_OFF) {
-            plan.any_exchange = true;
-            auto ci = reinterpret_cast<dpso::Inst *>(host.data() + BL.cls_inst[c]);
-            auto cf = reinterpret_cast<int32_t *>(host.data() + BL.cls_first[c]);
-            ci[cls_count[c]] = inst[i];
-            cf[cls_count[c]] = plan.cls_total[c];
-            cls_count[c] += 1;
-            plan.cls_total[c] += it.params.swarm_size;
-            plan.cls_max_ns[c] = std::max(plan.cls_max_ns[c], L.ns);
-        }
     }
     if (total > (int64_t(1) << 30)) return fail(DPSO_E_RANGE, "batch holds %lld particles", (long long)total);
+    std::vector<int> cls_members[dpso::kExchangeClasses], mv_members[kMoveClasses];
+    int64_t run = 0;
+    for (int32_t i = 0; i < count; ++i) {
+        const dpso_batch_item &it = items[i];
+        const dpso::Layout L = dpso::make_layout(it.n, it.params.swarm_size, it.params.max_generations + 1);
+        inst[i] = make_inst(it.d_dist, it.d_state, L, &it.params);
+        first_items[i] = int32_t(run);
+        first_inst[i] = i;
+        run += it.params.swarm_size;
+        plan.max_ns = std::max(plan.max_ns, L.ns);
+        plan.any_mutation |= it.params.mutation_period > 0;
+        const dpso::Tune tune = dpso::tuning_for(it.n, total);
+        mv_members[move_class(tune.move_threads, L.ns)].push_back(i);
+        if (it.params.ee_trigger != DPSO_EE_OFF) {
+            plan.any_exchange = true;
+            cls_members[dpso::exchange_class(it.n, it.d_dist, it.params.ee_neighbourhood, tune.exchange_rows)]
+                .push_back(i);
+        }
+    }
     first_items[count] = int32_t(total);
     first_inst[count] = count;
     unsigned char *dev = static_cast<unsigned char *>(d_work);
@@ -272,30 +355,152 @@ dpso_status plan_batch(const dpso_batch_item *items, int32_t count, void *d_work
                              reinterpret_cast<const int32_t *>(dev + BL.first_items), count};
     plan.instances = dpso::Batch{reinterpret_cast<const dpso::Inst *>(dev + BL.inst),
                                  reinterpret_cast<const int32_t *>(dev + BL.first_inst), count};
-    for (int c = 0; c < dpso::kExchangeClasses; ++c) {
-        reinterpret_cast<int32_t *>(host.data() + BL.cls_first[c])[cls_count[c]] = plan.cls_total[c];
-        plan.cls[c] = dpso::Batch{reinterpret_cast<const dpso::Inst *>(dev + BL.cls_inst[c]),
-                                  reinterpret_cast<const int32_t *>(dev + BL.cls_first[c]), cls_count[c]};
-    }
+    const int order = dpso::batch_order();
+    // a class's table in launch order (see order_class), its particle prefix
+    // and launch size
+    auto write_class = [&](ClassPlan &cp, const std::vector<int> &members, bool quadratic, size_t inst_off,
+                           size_t first_off) {
+        std::vector<int64_t> work(members.size()), swarm(members.size());
+        for (size_t k = 0; k < members.size(); ++k) {
+            const int64_t n = items[members[k]].n;
+            swarm[k] = items[members[k]].params.swarm_size;
+            work[k] = swarm[k] * (quadratic ? n * n : n);
+        }
+        const ClassOrder o = order_class(work, swarm, order);
+        auto ci = reinterpret_cast<dpso::Inst *>(host.data() + inst_off);
+        auto cf = reinterpret_cast<int32_t *>(host.data() + first_off);
+        int acc = 0;
+        for (size_t k = 0; k < o.order.size(); ++k) {
+            const int i = members[size_t(o.order[k])];
+            ci[k] = inst[i];
+            cf[k] = acc;
+            acc += items[i].params.swarm_size;
+            cp.max_ns = std::max(cp.max_ns, (items[i].n + 63) & ~63);
+        }
+        cf[o.order.size()] = acc;
+        cp.total = acc;
+        cp.members = dpso::Batch{reinterpret_cast<const dpso::Inst *>(dev + inst_off),
+                                 reinterpret_cast<const int32_t *>(dev + first_off), int32_t(members.size())};
+        cp.grid = acc;
+        if (o.groups) {
+            cp.members.groups = 8;
+            int base = 0, rows = 0;
+            for (int x = 0; x < 8; ++x) {
+                cp.members.xbase[x] = base;
+                cp.members.xcount[x] = o.xcount[x];
+                base += o.xcount[x];
+                rows = std::max(rows, o.xcount[x]);
+            }
+            cp.grid = 8 * rows;
+        }
+    };
+    for (int c = 0; c < dpso::kExchangeClasses; ++c)
+        write_class(plan.cls[c], cls_members[c], true, BL.cls_inst[c], BL.cls_first[c]);
+    for (int c = 0; c < kMoveClasses; ++c)
+        write_class(plan.mv[c], mv_members[c], false, BL.mv_inst[c], BL.mv_first[c]);
     HIP_TRY(hipMemcpyAsync(d_work, host.data(), host.size(), hipMemcpyHostToDevice, s), "copy batch tables");
     HIP_TRY(hipStreamSynchronize(s), "synchronise stream");
     return DPSO_OK;
 }
 
-// All launches of `generations` generations of a batch.
-hipError_t enqueue_batch(const BatchPlan &P, int32_t generations, hipStream_t s)
+// Fan-out of a phase's independent launches (one per move class, one per
+// exchange class): each goes to one of kFan library streams that wait for
+// `s` at a fork event, and `s` waits for all of them at join events. Under
+// stream capture the launches become parallel branches of the graph, so
+// classes overlap on the GPU instead of each waiting for the previous one's
+// last blocks. The streams are created once per device (non-blocking, default
+// priority); a device's fan is used by one call at a time (`lock`).
+constexpr int kFan = 8;
+
+struct Fan {
+    std::mutex lock;
+    bool ready = false;
+    hipStream_t st[kFan] = {};
+};
+
+Fan g_fans[64];
+
+struct FanEvents {
+    hipEvent_t fork = nullptr, join[kFan] = {};
+    ~FanEvents()
+    {
+        if (fork) (void)hipEventDestroy(fork);
+        for (hipEvent_t e : join)
+            if (e) (void)hipEventDestroy(e);
+    }
+};
+
+hipError_t fan_setup(Fan &f, FanEvents &ev)
+{
+    if (!f.ready) {
+        for (int k = 0; k < kFan; ++k) {
+            hipError_t e = hipStreamCreateWithFlags(&f.st[k], hipStreamNonBlocking);
+            if (e != hipSuccess) return e;
+        }
+        f.ready = true;
+    }
+    hipError_t e = hipEventCreateWithFlags(&ev.fork, hipEventDisableTiming);
+    for (int k = 0; k < kFan && e == hipSuccess; ++k) e = hipEventCreateWithFlags(&ev.join[k], hipEventDisableTiming);
+    return e;
+}
+
+// Launches launch(c, stream) for every class c in [0, classes) with members,
+// spread over the fan when more than one has members.
+template <class Launch>
+hipError_t fan_out(const ClassPlan *cls, int classes, Fan *f, FanEvents *ev, hipStream_t s, Launch launch)
+{
+    int used = 0;
+    for (int c = 0; c < classes; ++c) used += cls[c].members.count > 0;
+    if (used == 0) return hipSuccess;
+    if (used == 1 || !f) {
+        for (int c = 0; c < classes; ++c)
+            if (cls[c].members.count > 0) {
+                hipError_t e = launch(c, s);
+                if (e != hipSuccess) return e;
+            }
+        return hipSuccess;
+    }
+    hipError_t e = hipEventRecord(ev->fork, s);
+    bool waited[kFan] = {};
+    int k = 0;
+    for (int c = 0; c < classes && e == hipSuccess; ++c) {
+        if (cls[c].members.count == 0) continue;
+        const int j = k++ % kFan;
+        if (!waited[j]) {
+            e = hipStreamWaitEvent(f->st[j], ev->fork, 0);
+            waited[j] = true;
+        }
+        if (e == hipSuccess) e = launch(c, f->st[j]);
+    }
+    for (int j = 0; j < kFan && e == hipSuccess; ++j) {
+        if (!waited[j]) continue;
+        e = hipEventRecord(ev->join[j], f->st[j]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, ev->join[j], 0);
+    }
+    return e;
+}
+
+// All launches of `generations` generations of a batch; the move and
+// exchange classes fan out when `f` is given.
+hipError_t enqueue_batch(const BatchPlan &P, int32_t generations, hipStream_t s, Fan *f = nullptr,
+                         FanEvents *ev = nullptr)
 {
     hipError_t e = dpso::launch_batch_check(P.items, P.instances, P.total, P.max_ns, s);
     for (int c = 0; c < dpso::kExchangeClasses && e == hipSuccess && P.any_exchange; ++c)
-        e = dpso::launch_batch_2opt_prepare(c, P.cls[c], P.cls_max_ns[c], s);
+        e = dpso::launch_batch_2opt_prepare(c, P.cls[c].members, P.cls[c].max_ns, s);
+    auto move = [&](int c, hipStream_t st) {
+        return dpso::launch_batch_move(move_class_threads(c), P.mv[c].members, P.mv[c].grid, P.mv[c].max_ns, st);
+    };
+    auto exchange = [&](int c, hipStream_t st) {
+        return dpso::launch_batch_2opt(c, P.cls[c].members, P.cls[c].grid, P.cls[c].max_ns, st);
+    };
     for (int32_t g = 0; g < generations && e == hipSuccess; ++g) {
-        e = dpso::launch_batch_move(P.items, P.instances, P.total, P.max_ns, s);
+        e = fan_out(P.mv, kMoveClasses, f, ev, s, move);
         if (e == hipSuccess && P.any_mutation)
             e = dpso::launch_batch_mutation(P.items, P.instances, P.total, P.max_ns, s);
         if (e == hipSuccess) e = dpso::launch_batch_gbest(P.items, P.instances, P.total, P.max_ns, 1, s);
         if (P.any_exchange) {
-            for (int c = 0; c < dpso::kExchangeClasses && e == hipSuccess; ++c)
-                if (P.cls[c].count > 0) e = dpso::launch_batch_2opt(c, P.cls[c], P.cls_total[c], P.cls_max_ns[c], s);
+            if (e == hipSuccess) e = fan_out(P.cls, dpso::kExchangeClasses, f, ev, s, exchange);
             if (e == hipSuccess) e = dpso::launch_batch_gbest(P.items, P.instances, P.total, P.max_ns, 3, s);
         } else if (e == hipSuccess) {
             e = dpso::launch_batch_end(P.items, P.instances, P.total, P.max_ns, s);
@@ -324,7 +529,7 @@ dpso_status events(size_t count, std::vector<hipEvent_t> &out)
 // edge-exchange launches only (their summed time into times->ms_exchange).
 dpso_status run_impl(const int32_t *d_dist, int32_t n, const dpso_params *params, void *d_state,
                      size_t state_bytes, int32_t generations, void *stream, dpso_phase_times *times,
-                     bool exchange_only = false)
+                     bool exchange_only = false, const dpso::Tune *force = nullptr)
 {
     dpso_status st = check_params(params, n);
     if (st) return st;
@@ -335,6 +540,9 @@ dpso_status run_impl(const int32_t *d_dist, int32_t n, const dpso_params *params
         return fail(DPSO_E_NOMEM, "state buffer of %zu bytes, %zu needed", state_bytes, L.total);
     const dpso::Inst I = make_inst(d_dist, d_state, L, params);
     const dpso::KParams &kp = I.kp;
+    const dpso::Tune tune = force ? dpso::resolve_tuning(*force, n, params->swarm_size)
+                                  : dpso::tuning_for(n, params->swarm_size);
+    const int cls = dpso::exchange_class(n, d_dist, kp.ee_neighbourhood, tune.exchange_rows);
     hipStream_t s = as_stream(stream);
     std::vector<hipEvent_t> ev;
     constexpr int kMarks = 6;  // after move, mutation, gbest, exchange, gbest, end
@@ -346,17 +554,17 @@ dpso_status run_impl(const int32_t *d_dist, int32_t n, const dpso_params *params
     auto stamp = [&]() -> hipError_t { return all ? hipEventRecord(ev[mark++], s) : hipSuccess; };
     auto stamp_ex = [&]() -> hipError_t { return ex ? hipEventRecord(ev[mark++], s) : hipSuccess; };
     HIP_TRY(dpso::launch_check(I, s), "launch check");
-    if (kp.ee_trigger != DPSO_EE_OFF) HIP_TRY(dpso::launch_2opt_prepare(I, s), "launch exchange set-up");
+    if (kp.ee_trigger != DPSO_EE_OFF) HIP_TRY(dpso::launch_2opt_prepare(I, cls, s), "launch exchange set-up");
     HIP_TRY(stamp(), "record event");
     for (int32_t g = 0; g < generations; ++g) {
-        HIP_TRY(dpso::launch_move(I, s), "launch move");
+        HIP_TRY(dpso::launch_move(I, tune.move_threads, s), "launch move");
         HIP_TRY(stamp(), "record event");
         if (kp.mutation_period > 0) HIP_TRY(dpso::launch_mutation(I, s), "launch mutation");
         HIP_TRY(stamp(), "record event");
         HIP_TRY(dpso::launch_gbest(I, 1, s), "launch gbest");
         HIP_TRY(stamp(), "record event");
         HIP_TRY(stamp_ex(), "record event");
-        if (kp.ee_trigger != DPSO_EE_OFF) HIP_TRY(dpso::launch_2opt(I, s), "launch 2-opt");
+        if (kp.ee_trigger != DPSO_EE_OFF) HIP_TRY(dpso::launch_2opt(I, cls, s), "launch 2-opt");
         HIP_TRY(stamp(), "record event");
         HIP_TRY(stamp_ex(), "record event");
         // with the exchange on, the end of the generation runs in the global
@@ -463,9 +671,74 @@ dpso_status noalloc_scratch(void **out)
 
 }  // namespace
 
+// ------------------------------------------------------------ autotuner
+
+namespace {
+
+uint64_t fnv1a(uint64_t h, const void *data, size_t bytes)
+{
+    const unsigned char *p = static_cast<const unsigned char *>(data);
+    for (size_t k = 0; k < bytes; ++k) {
+        h ^= p[k];
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+// Digest of what a run computes: the swarm's tours, personal bests,
+// velocities and costs (the first n labels of each row, or the stored
+// transpositions of a raw velocity), the global best, the trace and the
+// header's progress counters. Scratch regions (mutation marks, the 16-bit
+// copy of D) are left out. Synchronises the stream.
+dpso_status state_digest(const void *d_state, hipStream_t s, uint64_t *out)
+{
+    dpso::Hdr h;
+    dpso_status st = read_header(d_state, &h, s);
+    if (st) return st;
+    const dpso::Layout L = dpso::make_layout(h.n, h.S, h.cap);
+    const char *b = static_cast<const char *>(d_state);
+    const size_t S = size_t(h.S), ns = size_t(L.ns), n = size_t(h.n);
+    std::vector<uint16_t> X(S * ns), P(S * ns), V(S * 2 * ns), G(ns);
+    std::vector<int32_t> VL(S);
+    std::vector<int64_t> F(S), FP(S), trace(size_t(h.t) + 1);
+    HIP_TRY(hipMemcpyAsync(X.data(), b + L.X, X.size() * 2, hipMemcpyDeviceToHost, s), "copy X");
+    HIP_TRY(hipMemcpyAsync(P.data(), b + L.P, P.size() * 2, hipMemcpyDeviceToHost, s), "copy P");
+    HIP_TRY(hipMemcpyAsync(V.data(), b + L.V, V.size() * 2, hipMemcpyDeviceToHost, s), "copy V");
+    HIP_TRY(hipMemcpyAsync(VL.data(), b + L.VL, S * 4, hipMemcpyDeviceToHost, s), "copy VL");
+    HIP_TRY(hipMemcpyAsync(F.data(), b + L.F, S * 8, hipMemcpyDeviceToHost, s), "copy F");
+    HIP_TRY(hipMemcpyAsync(FP.data(), b + L.FP, S * 8, hipMemcpyDeviceToHost, s), "copy FP");
+    HIP_TRY(hipMemcpyAsync(G.data(), b + L.G, ns * 2, hipMemcpyDeviceToHost, s), "copy G");
+    HIP_TRY(hipMemcpyAsync(trace.data(), b + L.trace, trace.size() * 8, hipMemcpyDeviceToHost, s), "copy trace");
+    HIP_TRY(hipStreamSynchronize(s), "synchronise stream");
+    uint64_t d = 14695981039346656037ull;
+    const int64_t counters[] = {h.t, h.stall, h.done, h.FG, int64_t(h.n_sweeps), int64_t(h.n_moves),
+                                int64_t(h.n_reshuffled)};
+    d = fnv1a(d, counters, sizeof counters);
+    for (size_t p = 0; p < S; ++p) {
+        d = fnv1a(d, X.data() + p * ns, n * 2);
+        d = fnv1a(d, P.data() + p * ns, n * 2);
+        const uint16_t *v = V.data() + p * 2 * ns;
+        if (h.velocity_cap > 0) {
+            d = fnv1a(d, v, size_t(std::max(VL[p], 0)) * 4);
+        } else if (VL[p]) {
+            d = fnv1a(d, v, n * 2);
+            d = fnv1a(d, v + ns, n * 2);
+        }
+    }
+    d = fnv1a(d, VL.data(), S * 4);
+    d = fnv1a(d, F.data(), S * 8);
+    d = fnv1a(d, FP.data(), S * 8);
+    d = fnv1a(d, G.data(), n * 2);
+    d = fnv1a(d, trace.data(), trace.size() * 8);
+    *out = d;
+    return DPSO_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
-const char *dpso_version(void) { return "dpso-mi355x 0.1 (gfx950)"; }
+const char *dpso_version(void) { return "dpso-mi355x 0.2 (gfx950)"; }
 
 const char *dpso_last_error(void) { return dpso::last_error(); }
 
@@ -559,6 +832,104 @@ dpso_status dpso_run_timed(const int32_t *d_dist, int32_t n, const dpso_params *
 {
     if (!times) return fail(DPSO_E_INVAL, "times must be non-NULL");
     return run_impl(d_dist, n, params, d_state, state_bytes, generations, stream, times, true);
+}
+
+dpso_status dpso_autotune(const int32_t *d_dist, int32_t n, const dpso_params *params, void *d_state,
+                          size_t state_bytes, int32_t generations, void *d_scratch, size_t scratch_bytes,
+                          dpso_tune_result *results, int32_t max_results, int32_t *n_results,
+                          dpso_tuning *chosen, void *stream)
+{
+    dpso_status st = check_params(params, n);
+    if (st) return st;
+    if (!d_dist || !d_state || !d_scratch) return fail(DPSO_E_INVAL, "d_dist, d_state and d_scratch must be non-NULL");
+    if (generations < 1) return fail(DPSO_E_INVAL, "generations must be >= 1");
+    if (max_results < 0 || (max_results > 0 && !results)) return fail(DPSO_E_INVAL, "bad results array");
+    const dpso::Layout L = dpso::make_layout(n, params->swarm_size, params->max_generations + 1);
+    if (state_bytes < L.total) return fail(DPSO_E_NOMEM, "state buffer of %zu bytes, %zu needed", state_bytes, L.total);
+    if (scratch_bytes < L.total) return fail(DPSO_E_NOMEM, "scratch of %zu bytes, %zu needed", scratch_bytes, L.total);
+    hipStream_t s = as_stream(stream);
+    dpso::Hdr h;
+    if ((st = read_header(d_state, &h, s))) return st;
+    if (h.n != n || h.S != params->swarm_size) return fail(DPSO_E_STATE, "state does not hold n = %d, swarm %d", n, params->swarm_size);
+    if (int64_t(h.t) + generations > params->max_generations)
+        return fail(DPSO_E_RANGE, "the state is at generation %d: %d more pass max_generations = %d", h.t,
+                    generations, params->max_generations);
+    HIP_TRY(hipMemcpyAsync(d_scratch, d_state, L.total, hipMemcpyDeviceToDevice, s), "snapshot state");
+    hipEvent_t ev[2];
+    std::vector<hipEvent_t> pool;
+    if ((st = events(2, pool))) return st;
+    ev[0] = pool[0];
+    ev[1] = pool[1];
+    const dpso::Tune dflt = dpso::default_tuning(n, params->swarm_size);
+    std::vector<dpso_tune_result> done;
+    // one candidate: two timed runs from the snapshot, the digest of the second
+    auto trial = [&](const dpso::Tune &t) -> dpso_status {
+        dpso_tune_result r{};
+        r.config.move_threads = t.move_threads;
+        r.config.exchange_rows = t.exchange_rows;
+        r.ms = -1.f;
+        for (int rep = 0; rep < 2; ++rep) {
+            HIP_TRY(hipMemcpyAsync(d_state, d_scratch, L.total, hipMemcpyDeviceToDevice, s), "restore state");
+            HIP_TRY(hipEventRecord(ev[0], s), "record event");
+            dpso_status rs = run_impl(d_dist, n, params, d_state, state_bytes, generations, stream, nullptr, false, &t);
+            if (rs) return rs;
+            HIP_TRY(hipEventRecord(ev[1], s), "record event");
+            HIP_TRY(hipEventSynchronize(ev[1]), "synchronise event");
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, ev[0], ev[1]), "event time");
+            if (r.ms < 0.f || ms < r.ms) r.ms = ms;
+        }
+        dpso_status ds = state_digest(d_state, s, &r.digest);
+        if (ds) return ds;
+        done.push_back(r);
+        return DPSO_OK;
+    };
+    auto finish = [&](dpso_status code) -> dpso_status {
+        // leave the state as it was, whatever happened
+        const hipError_t e1 = hipMemcpyAsync(d_state, d_scratch, L.total, hipMemcpyDeviceToDevice, s);
+        const hipError_t e2 = hipStreamSynchronize(s);
+        if (code == DPSO_OK && e1 != hipSuccess) return hip_fail(e1, "restore state");
+        if (code == DPSO_OK && e2 != hipSuccess) return hip_fail(e2, "synchronise stream");
+        return code;
+    };
+    // phase 1: threads per particle in the move, the exchange at its default
+    const int ns = L.ns;
+    for (int tpb : {64, 128, 256}) {
+        if (!dpso::move_threads_ok(tpb, ns)) continue;
+        st = trial(dpso::Tune{tpb, dflt.exchange_rows});
+        if (st) return finish(st);
+    }
+    size_t best = 0;
+    for (size_t k = 1; k < done.size(); ++k)
+        if (done[k].ms < done[best].ms) best = k;
+    // phase 2: the exchange's row form with the fastest move
+    const bool exchange = params->ee_trigger != DPSO_EE_OFF && params->ee_neighbourhood == DPSO_NB_TWO_OPT;
+    if (exchange) {
+        const int tpb = done[best].config.move_threads;
+        for (int rows : {DPSO_ROWS_U16, DPSO_ROWS_I32, DPSO_ROWS_BLOCK}) {
+            if (rows == dflt.exchange_rows) continue;
+            if (rows == DPSO_ROWS_U16 && !dpso::packed_rows(n)) continue;
+            if (rows == DPSO_ROWS_I32 && n > 1024) continue;
+            // an n off 16 bytes takes 16-bit rows for int32 ones: the same kernel
+            if (rows == DPSO_ROWS_I32 && (n & 3) != 0 && dpso::packed_rows(n)) continue;
+            st = trial(dpso::Tune{tpb, rows});
+            if (st) return finish(st);
+        }
+    }
+    for (size_t k = 0; k < done.size(); ++k) {
+        if (done[k].digest != done[0].digest)
+            return finish(fail(DPSO_E_STATE, "configurations disagree: %d threads / rows %d and %d threads / rows %d",
+                               done[0].config.move_threads, done[0].config.exchange_rows,
+                               done[k].config.move_threads, done[k].config.exchange_rows));
+        if (done[k].ms < done[best].ms) best = k;
+    }
+    st = finish(DPSO_OK);
+    if (st) return st;
+    if ((st = dpso_tuning_set(n, params->swarm_size, &done[best].config))) return st;
+    for (int32_t k = 0; k < max_results && size_t(k) < done.size(); ++k) results[k] = done[size_t(k)];
+    if (n_results) *n_results = int32_t(done.size());
+    if (chosen) *chosen = done[best].config;
+    return ok();
 }
 
 dpso_status dpso_get_info(const void *d_state, dpso_info *info, void *stream)
@@ -753,12 +1124,18 @@ dpso_status dpso_run_batch(const dpso_batch_item *items, int32_t count, int32_t 
     dpso_status st = plan_batch(items, count, d_work, work_bytes, as_stream(stream), plan);
     if (st) return st;
     hipStream_t s = as_stream(stream);
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev), "current device");
+    Fan &fan = g_fans[dev >= 0 && dev < 64 ? dev : 0];
+    std::lock_guard<std::mutex> hold(fan.lock);
+    FanEvents ev;
+    HIP_TRY(fan_setup(fan, ev), "fan-out streams");
     // the whole run as one graph when the stream can be captured
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     const bool graph = s != nullptr && hipStreamIsCapturing(s, &cap) == hipSuccess &&
                        cap == hipStreamCaptureStatusNone && generations > 0;
     if (graph) HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "begin capture");
-    hipError_t e = enqueue_batch(plan, generations, s);
+    hipError_t e = enqueue_batch(plan, generations, s, &fan, &ev);
     if (graph) {
         hipGraph_t g = nullptr;
         const hipError_t ec = hipStreamEndCapture(s, &g);

@@ -133,6 +133,15 @@ __device__ inline T *global_ptr(T *p)
 // Instance and local index of block b in a batched launch (binary search
 // over the prefix table; uniform across the workgroup). The descriptor's
 // pointers are returned marked as global.
+// The item block b of a batched launch works on, or -1 for a block past
+// the end of its XCD group (it does nothing).
+__device__ inline int batch_item(const Batch &B, int b)
+{
+    if (B.groups == 0) return b;
+    const int x = b & 7, k = b >> 3;
+    return k < B.xcount[x] ? B.xbase[x] + k : -1;
+}
+
 __device__ inline Inst batch_pick(const Batch &B, int b, int &local)
 {
     int lo = 0, hi = B.count - 1;

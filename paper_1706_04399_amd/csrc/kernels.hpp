@@ -4,13 +4,17 @@
 #include <hip/hip_runtime.h>
 
 #include "state.hpp"
+#include "tune.hpp"
 
 namespace dpso {
 
 // swarm.hip: one instance (descriptor by value)
 hipError_t launch_init(const Inst &I, hipStream_t s);
 hipError_t launch_check(const Inst &I, hipStream_t s);
-hipError_t launch_move(const Inst &I, hipStream_t s);
+// the move at tpb (64, 128 or 256) threads per particle; move_threads_ok
+// tells whether tpb serves row stride ns (at most 16 positions per thread)
+bool move_threads_ok(int tpb, int ns);
+hipError_t launch_move(const Inst &I, int tpb, hipStream_t s);
 hipError_t launch_mutation(const Inst &I, hipStream_t s);
 hipError_t launch_gbest(const Inst &I, int mode, hipStream_t s);
 hipError_t launch_end(const Inst &I, hipStream_t s);
@@ -19,7 +23,8 @@ hipError_t launch_end(const Inst &I, hipStream_t s);
 // blocks), `instances` one block per instance; max_ns sizes dynamic LDS.
 hipError_t launch_batch_init(const Batch &items, const Batch &instances, int total, int max_ns, hipStream_t s);
 hipError_t launch_batch_check(const Batch &items, const Batch &instances, int total, int max_ns, hipStream_t s);
-hipError_t launch_batch_move(const Batch &items, const Batch &instances, int total, int max_ns, hipStream_t s);
+// the move of one move class (instances sharing tpb; `items` its table)
+hipError_t launch_batch_move(int tpb, const Batch &items, int total, int max_ns, hipStream_t s);
 hipError_t launch_batch_mutation(const Batch &items, const Batch &instances, int total, int max_ns,
                                  hipStream_t s);
 hipError_t launch_batch_gbest(const Batch &items, const Batch &instances, int total, int max_ns, int mode,
@@ -27,16 +32,16 @@ hipError_t launch_batch_gbest(const Batch &items, const Batch &instances, int to
 hipError_t launch_batch_end(const Batch &items, const Batch &instances, int total, int max_ns, hipStream_t s);
 
 // twoopt.hip: the edge-exchange kernel depends on the neighbourhood, on n
-// (columns held per lane) and on the alignment of D; instances of one class
-// share a launch. The last class is the node-swap neighbourhood.
+// (columns held per lane), on the row form of the configuration and on the
+// alignment of D (exchange_class, tune.hpp); instances of one class share a
+// launch. The last class is the node-swap neighbourhood.
 constexpr int kExchangeClasses = 17;
-int exchange_class(int n, const int32_t *D, int neighbourhood);
-hipError_t launch_2opt(const Inst &I, hipStream_t s);
+hipError_t launch_2opt(const Inst &I, int cls, hipStream_t s);
 hipError_t launch_batch_2opt(int cls, const Batch &items, int total, int max_ns, hipStream_t s);
 // Per-run set-up of the exchange: classes that stage 16-bit rows refresh the
 // state's packed copy of D (after the run's first launch, which clears the
 // header's maximum). `members` is a class's instance table; max_n bounds n.
-hipError_t launch_2opt_prepare(const Inst &I, hipStream_t s);
+hipError_t launch_2opt_prepare(const Inst &I, int cls, hipStream_t s);
 hipError_t launch_batch_2opt_prepare(int cls, const Batch &members, int max_n, hipStream_t s);
 
 // nodeswap.hip: the node-swap neighbourhood (one workgroup per particle).

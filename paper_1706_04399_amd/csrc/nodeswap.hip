@@ -122,7 +122,9 @@ __global__ __launch_bounds__(kThreads) void k_node_swap(Inst I) { node_swap_body
 __global__ __launch_bounds__(kThreads) void k_node_swap_batch(Batch B)
 {
     int p;
-    const Inst &I = batch_pick(B, int(blockIdx.x), p);
+    const int b = batch_item(B, int(blockIdx.x));
+    if (b < 0) return;
+    const Inst &I = batch_pick(B, b, p);
     node_swap_body(I, p);
 }
 

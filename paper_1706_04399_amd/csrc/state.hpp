@@ -15,8 +15,9 @@
 //   flags  int32  [S]      mutation scratch: duplicate marks
 //   keep   int32  [S]      mutation scratch: kept marks
 //   H      uint16 [n][hs]  D >> shift with rows padded to hs = n rounded up to
-//                          8 (zeros), the rows the edge exchange stages when
-//                          packed_rows(n) (else empty); rewritten by every run
+//                          8 (zeros), the rows the 16-bit edge exchange stages,
+//                          held when packed_rows(n) (else empty); rewritten by
+//                          every run that uses it
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -44,16 +45,11 @@ struct Hdr {
     int32_t pad;
 };
 
-// The edge exchange stages 16-bit rows (H = D >> shift, padded rows of
-// 2 hs bytes that start on 16 bytes) for these n: a sweep fits one
-// wavefront, and either a row takes fewer 1 KB load chunks than an int32 row
-// (n > 256) or int32 rows of D do not start on 16 bytes (n not a multiple of
-// 4) and would have to pass through registers. At n <= 256, n a multiple of
-// 4, int32 rows of D go straight into LDS in one chunk already.
-__host__ __device__ inline bool packed_rows(int32_t n)
-{
-    return n >= 8 && n <= 1024 && (n > 256 || (n & 3) != 0);
-}
+// The edge exchange can stage 16-bit rows (H = D >> shift, padded rows of
+// 2 hs bytes that start on 16 bytes) for these n, where a sweep fits one
+// wavefront; the state holds H for them.
+__host__ __device__ inline bool packed_rows(int32_t n) { return n >= 8 && n <= 1024; }
+
 __host__ __device__ inline int32_t packed_stride(int32_t n) { return (n + 7) & ~7; }
 
 // shift that brings the largest entry of D under 2^16
@@ -149,6 +145,14 @@ struct Batch {
     const Inst *inst;
     const int32_t *first;  // [count + 1]
     int32_t count;
+    // XCD groups of a per-particle launch (groups == 8): workgroups are
+    // handed to the eight XCDs in turn, so block b runs on XCD b mod 8 and
+    // works on item xbase[b & 7] + (b >> 3) of that XCD's group while below
+    // xcount[b & 7]; the members of a group are contiguous in the table, so
+    // each instance's particles share one XCD's L2. groups == 0: block b is
+    // item b.
+    int32_t groups;
+    int32_t xbase[8], xcount[8];
 };
 
 }  // namespace dpso

@@ -249,7 +249,9 @@ __device__ __forceinline__ void init_body(const Inst &I, int p)
 // the move); its transposition list is the canonical to - from.
 namespace {
 
-constexpr int kMoveThreads = 256;
+// Threads per particle of the move (TPB, a template argument): 64, 128 or
+// 256; every loop takes EPT = ceil(ns / TPB) positions per thread.
+constexpr int kMaxMoveThreads = 256;
 constexpr uint16_t kEmit = 1u << 14;   // in rho[p]: p is not the largest of its cycle
 constexpr uint16_t kFixed = 1u << 15;  // in rho[p]: p is among the first k of those
 constexpr uint16_t kLabel = 0x0fff;    // labels and positions (n <= 4096)
@@ -302,10 +304,11 @@ __device__ MoveLds carve_move_lds(unsigned char *base, int nl)
 
 // Exclusive prefix count of the kEmit marks of rho[0..n) into rank[];
 // returns the total. Each thread takes a contiguous chunk.
+template <int TPB>
 __device__ __forceinline__ int block_rank(const uint16_t *rho, uint16_t *rank, int n, int *wsum)
 {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int chunk = (n + kMoveThreads - 1) / kMoveThreads;
+    const int chunk = (n + TPB - 1) / TPB;
     const int lo = min(n, tid * chunk), hi = min(n, lo + chunk);
     int c = 0;
     for (int p = lo; p < hi; ++p) c += (rho[p] & kEmit) != 0;
@@ -318,7 +321,7 @@ __device__ __forceinline__ int block_rank(const uint16_t *rho, uint16_t *rank, i
     if (lane == 63) wsum[wave] = incl;
     __syncthreads();
     int base = 0, total = 0;
-    for (int w = 0; w < kMoveThreads / 64; ++w) {
+    for (int w = 0; w < TPB / 64; ++w) {
         base += w < wave ? wsum[w] : 0;
         total += wsum[w];
     }
@@ -331,19 +334,19 @@ __device__ __forceinline__ int block_rank(const uint16_t *rho, uint16_t *rank, i
     return total;
 }
 
-// The move kernel's loops visit the positions tid, tid + 256, ... of one
-// thread; EPT (elements per thread, ceil(n / 256) rounded up to a power of
+// The move kernel's loops visit the positions tid, tid + TPB, ... of one
+// thread; EPT (elements per thread, ceil(ns / TPB) rounded up to a power of
 // two) is a compile-time bound, so every loop is unrolled and the LDS reads of
 // a pointer-jumping round are all in flight together.
 #define DPSO_EACH(p)                                                                   \
-    _Pragma("unroll") for (int e_ = 0, p = int(threadIdx.x); e_ < EPT; ++e_, p += kMoveThreads) \
+    _Pragma("unroll") for (int e_ = 0, p = int(threadIdx.x); e_ < EPT; ++e_, p += TPB) \
         if (p < n)
 
 // cur <- from + (first k transpositions of the canonical to - from), with
 // k = pick(length). posf is the inverse of from. Returns the length, or -1
 // when `whole` says the prefix is the whole list whatever its length (then
 // cur = to and nothing else is computed).
-template <int EPT, class Pick>
+template <int TPB, int EPT, class Pick>
 __device__ __forceinline__ int partial_toward(const uint16_t *from, const uint16_t *posf, const uint16_t *to, int n,
                               Pick pick, bool whole, MoveLds &L)
 {
@@ -385,7 +388,7 @@ __device__ __forceinline__ int partial_toward(const uint16_t *from, const uint16
     if ((e[e_] >> 16) != uint32_t(p)) L.rho[p] |= kEmit;
     __syncthreads();
     uint16_t *rank = reinterpret_cast<uint16_t *>(eb);  // eb is free here
-    const int len = block_rank(L.rho, rank, n, L.wsum);
+    const int len = block_rank<TPB>(L.rho, rank, n, L.wsum);
     const int k = pick(len);
     if (k <= 0 || k >= len) {
         const uint16_t *src = k <= 0 ? from : to;
@@ -559,7 +562,7 @@ __device__ __forceinline__ void move_raw_body(const Inst &I, int part)
     }
 }
 
-template <int EPT>
+template <int TPB, int EPT>
 __device__ __forceinline__ void move_body(const Inst &I, int part)
 {
     const int32_t *__restrict__ D = I.D;
@@ -577,7 +580,7 @@ __device__ __forceinline__ void move_body(const Inst &I, int part)
     // cost at the end, after the last one
     const int64_t fp_old = st.FP[part];
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ int64_t redi[kMoveThreads / 64];
+    __shared__ int64_t redi[TPB / 64];
     __shared__ uint64_t draw0;  // first 64-bit word of stream (part, t, vel)
     MoveLds L = carve_move_lds(smem, (n + 7) & ~7);
     if (tid < 3) L.vote[tid] = 0;  // ordered before the first vote by the barriers below
@@ -605,7 +608,7 @@ __device__ __forceinline__ void move_body(const Inst &I, int part)
     const bool whole_w = kp.w_q16 >= 65536u;
     // z <- w(z): the prefix of the stored velocity as a label map
     if (has_v) {
-        partial_toward<EPT>(L.from, L.posf, L.to, n,
+        partial_toward<TPB, EPT>(L.from, L.posf, L.to, n,
                             [&](int len) {
                                 const uint64_t k = (uint64_t(kp.w_q16) * uint64_t(len)) >> 16;
                                 return k < uint64_t(len) ? int(k) : len;
@@ -623,7 +626,7 @@ __device__ __forceinline__ void move_body(const Inst &I, int part)
     }
     __syncthreads();
     // z <- b(z), b the prefix of P - x
-    partial_toward<EPT>(L.x, L.posx, L.to, n, [&](int len) { return prefix_count(kp.phi1_q16, r1, len); },
+    partial_toward<TPB, EPT>(L.x, L.posx, L.to, n, [&](int len) { return prefix_count(kp.phi1_q16, r1, len); },
                         whole_b, L);
     DPSO_EACH(k)
     {
@@ -632,7 +635,7 @@ __device__ __forceinline__ void move_body(const Inst &I, int part)
     }
     __syncthreads();
     // z <- c(z), c the prefix of G - x
-    partial_toward<EPT>(L.x, L.posx, L.to, n, [&](int len) { return prefix_count(kp.phi2_q16, r2, len); },
+    partial_toward<TPB, EPT>(L.x, L.posx, L.to, n, [&](int len) { return prefix_count(kp.phi2_q16, r2, len); },
                         whole_c, L);
     DPSO_EACH(k) L.z[k] = L.cur[L.posx[L.z[k]]];
     __syncthreads();
@@ -833,19 +836,16 @@ __device__ __forceinline__ void gbest2_end_body(const Inst &I)
     }                                                                                        \
     __global__ __launch_bounds__(threads) void name##_batch(Batch B)                         \
     {                                                                                        \
+        const int b = batch_item(B, int(blockIdx.x));                                        \
+        if (b < 0) return;                                                                   \
         int item;                                                                            \
-        const Inst &I = batch_pick(B, int(blockIdx.x), item);                                \
+        const Inst &I = batch_pick(B, b, item);                                              \
         call;                                                                                \
     }
 
 DPSO_KERNELS(k_hdr_init, 64, hdr_init_body(I))
 DPSO_KERNELS(k_hdr_check, 64, hdr_check_body(I))
 DPSO_KERNELS(k_init, 256, init_body(I, item))
-DPSO_KERNELS(k_move1, kMoveThreads, move_body<1>(I, item))
-DPSO_KERNELS(k_move2, kMoveThreads, move_body<2>(I, item))
-DPSO_KERNELS(k_move4, kMoveThreads, move_body<4>(I, item))
-DPSO_KERNELS(k_move8, kMoveThreads, move_body<8>(I, item))
-DPSO_KERNELS(k_move16, kMoveThreads, move_body<16>(I, item))
 DPSO_KERNELS(k_mut_dup, 64, mut_dup_body(I, item))
 DPSO_KERNELS(k_mut_keep, 64, mut_keep_body(I, item))
 DPSO_KERNELS(k_mut_apply, 256, mut_apply_body(I, item))
@@ -856,6 +856,22 @@ DPSO_KERNELS(k_end, 64, end_body(I))
 DPSO_KERNELS(k_gbest2_end, 1024, gbest2_end_body(I))
 
 #undef DPSO_KERNELS
+
+// The move at TPB threads per particle and EPT positions per thread.
+template <int TPB, int EPT>
+__global__ __launch_bounds__(TPB) void k_move(Inst I)
+{
+    move_body<TPB, EPT>(I, int(blockIdx.x));
+}
+template <int TPB, int EPT>
+__global__ __launch_bounds__(TPB) void k_move_batch(Batch B)
+{
+    const int b = batch_item(B, int(blockIdx.x));
+    if (b < 0) return;
+    int item;
+    const Inst &I = batch_pick(B, b, item);
+    move_body<TPB, EPT>(I, item);
+}
 
 // ---------------------------------------------------------------- launchers
 
@@ -915,16 +931,35 @@ hipError_t launch_check_t(const Target &t, hipStream_t s)
     return launch(k_hdr_check, k_hdr_check_batch, t, false, 64, 0, s);
 }
 
-hipError_t launch_move_t(const Target &t, hipStream_t s)
+namespace {
+
+template <int TPB>
+hipError_t launch_move_tpb(const Target &t, size_t lds, hipStream_t s)
+{
+    const int ept = (t.max_ns + TPB - 1) / TPB;
+    if (ept <= 1) return launch(k_move<TPB, 1>, k_move_batch<TPB, 1>, t, true, TPB, lds, s);
+    if (ept <= 2) return launch(k_move<TPB, 2>, k_move_batch<TPB, 2>, t, true, TPB, lds, s);
+    if (ept <= 4) return launch(k_move<TPB, 4>, k_move_batch<TPB, 4>, t, true, TPB, lds, s);
+    if (ept <= 8) return launch(k_move<TPB, 8>, k_move_batch<TPB, 8>, t, true, TPB, lds, s);
+    if (ept <= 16) return launch(k_move<TPB, 16>, k_move_batch<TPB, 16>, t, true, TPB, lds, s);
+    return hipErrorInvalidConfiguration;  // more than 16 positions per thread
+}
+
+}  // namespace
+
+bool move_threads_ok(int tpb, int ns)
+{
+    return (tpb == 64 || tpb == 128 || tpb == 256) && ns <= 16 * tpb;
+}
+
+hipError_t launch_move_t(const Target &t, int tpb, hipStream_t s)
 {
     // a single instance sizes LDS by its n; a batch by its largest row stride
     const size_t lds = t.one ? move_lds_bytes(t.one->st.n, t.one->st.ns) : move_lds_bytes(t.max_ns, t.max_ns);
-    const int ept = (t.max_ns + kMoveThreads - 1) / kMoveThreads;
-    if (ept <= 1) return launch(k_move1, k_move1_batch, t, true, kMoveThreads, lds, s);
-    if (ept <= 2) return launch(k_move2, k_move2_batch, t, true, kMoveThreads, lds, s);
-    if (ept <= 4) return launch(k_move4, k_move4_batch, t, true, kMoveThreads, lds, s);
-    if (ept <= 8) return launch(k_move8, k_move8_batch, t, true, kMoveThreads, lds, s);
-    return launch(k_move16, k_move16_batch, t, true, kMoveThreads, lds, s);
+    if (!move_threads_ok(tpb, t.max_ns)) return hipErrorInvalidConfiguration;
+    if (tpb == 64) return launch_move_tpb<64>(t, lds, s);
+    if (tpb == 128) return launch_move_tpb<128>(t, lds, s);
+    return launch_move_tpb<256>(t, lds, s);
 }
 
 hipError_t launch_mutation_t(const Target &t, hipStream_t s)
@@ -951,7 +986,7 @@ hipError_t launch_end_t(const Target &t, hipStream_t s)
 // Single-instance entry points.
 hipError_t launch_init(const Inst &I, hipStream_t s) { return launch_init_t(single(I), s); }
 hipError_t launch_check(const Inst &I, hipStream_t s) { return launch_check_t(single(I), s); }
-hipError_t launch_move(const Inst &I, hipStream_t s) { return launch_move_t(single(I), s); }
+hipError_t launch_move(const Inst &I, int tpb, hipStream_t s) { return launch_move_t(single(I), tpb, s); }
 hipError_t launch_mutation(const Inst &I, hipStream_t s) { return launch_mutation_t(single(I), s); }
 hipError_t launch_gbest(const Inst &I, int mode, hipStream_t s) { return launch_gbest_t(single(I), mode, s); }
 hipError_t launch_end(const Inst &I, hipStream_t s) { return launch_end_t(single(I), s); }
@@ -968,10 +1003,10 @@ hipError_t launch_batch_check(const Batch &items, const Batch &instances, int to
     Target t{nullptr, items, instances, total, instances.count, max_ns};
     return launch_check_t(t, s);
 }
-hipError_t launch_batch_move(const Batch &items, const Batch &instances, int total, int max_ns, hipStream_t s)
+hipError_t launch_batch_move(int tpb, const Batch &items, int total, int max_ns, hipStream_t s)
 {
-    Target t{nullptr, items, instances, total, instances.count, max_ns};
-    return launch_move_t(t, s);
+    Target t{nullptr, items, Batch{}, total, items.count, max_ns};
+    return launch_move_t(t, tpb, s);
 }
 hipError_t launch_batch_mutation(const Batch &items, const Batch &instances, int total, int max_ns,
                                  hipStream_t s)

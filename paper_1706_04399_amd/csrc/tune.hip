@@ -1,0 +1,169 @@
+// The launch-configuration table: one per device, filled by the autotuner
+// (dpso_autotune) or by the caller (dpso_tuning_set), read on every run.
+#include <mutex>
+
+#include "dpso.h"
+#include "errors.hpp"
+#include "kernels.hpp"
+#include "tune.hpp"
+
+namespace dpso {
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+
+struct Table {
+    Tune entry[kTuneNBuckets][kTunePBuckets];  // {0, 0}: empty
+    int order;                                 // DPSO_ORDER_*, 0: default
+};
+
+constexpr int kDefaultOrder = DPSO_ORDER_LPT;
+
+std::mutex g_table_mutex;
+Table g_tables[kMaxDevices];
+
+int current_device()
+{
+    int d = 0;
+    if (hipGetDevice(&d) != hipSuccess || d < 0 || d >= kMaxDevices) d = 0;
+    return d;
+}
+
+int bucket_max_n(int b) { return b >= 12 ? 4096 : 1 << b; }
+
+}  // namespace
+
+int tune_bucket_n(int n)
+{
+    int b = 1;
+    while (b < 12 && n > (1 << b)) ++b;
+    return b;
+}
+
+int tune_bucket_p(int64_t particles)
+{
+    return particles <= 128 ? 0 : particles <= 512 ? 1 : particles <= 1024 ? 2 : particles <= 2048 ? 3
+                                                                               : particles <= 8192 ? 4 : 5;
+}
+
+// Built-in choices, from the autotuner's measurements on MI355X (facades,
+// edge exchange every generation): with more than 2048 particles in flight
+// the GPU is full whatever the width, and one wavefront per particle in the
+// move is fastest up to n = 512 (5-10 % faster generations than 256 threads
+// at n <= 192); a lone small swarm is latency-bound and one wavefront has the
+// cheapest barriers; in between 256 threads fill the GPU best. int32 rows
+// straight into LDS beat 16-bit rows up to n = 512 (n a multiple of 4); above
+// that the 16-bit rows' halved staging wins.
+Tune default_tuning(int n, int64_t particles)
+{
+    Tune t;
+    const int ns = (n + 63) & ~63;
+    if (particles > 2048)
+        t.move_threads = n <= 512 ? 64 : 256;
+    else if (particles <= 128)
+        t.move_threads = move_threads_ok(64, ns) ? 64 : 256;
+    else
+        t.move_threads = 256;
+    const bool aligned = (n & 3) == 0;
+    t.exchange_rows = n > 1024 ? DPSO_ROWS_BLOCK
+                      : !packed_rows(n) || (aligned && n <= 512) ? DPSO_ROWS_I32
+                                                                 : DPSO_ROWS_U16;
+    return t;
+}
+
+// int32 rows of an n that is not a multiple of 4 do not start on 16 bytes and
+// would pass through registers, several times slower than 16-bit rows: such
+// an n takes 16-bit rows whenever it has them (a bucket's pick is made on an
+// aligned n).
+Tune resolve_tuning(Tune t, int n, int64_t particles)
+{
+    const Tune d = default_tuning(n, particles);
+    const int ns = (n + 63) & ~63;
+    if (!move_threads_ok(t.move_threads, ns)) t.move_threads = d.move_threads;
+    if (t.exchange_rows == DPSO_ROWS_I32 && (n & 3) != 0 && packed_rows(n)) t.exchange_rows = DPSO_ROWS_U16;
+    const bool ok = t.exchange_rows == DPSO_ROWS_BLOCK || (t.exchange_rows == DPSO_ROWS_I32 && n <= 1024) ||
+                    (t.exchange_rows == DPSO_ROWS_U16 && packed_rows(n));
+    if (!ok) t.exchange_rows = d.exchange_rows;
+    return t;
+}
+
+int batch_order()
+{
+    std::lock_guard<std::mutex> lock(g_table_mutex);
+    const int o = g_tables[current_device()].order;
+    return o == DPSO_ORDER_DEFAULT ? kDefaultOrder : o;
+}
+
+Tune tuning_for(int n, int64_t particles)
+{
+    Tune t{0, 0};
+    {
+        std::lock_guard<std::mutex> lock(g_table_mutex);
+        t = g_tables[current_device()].entry[tune_bucket_n(n)][tune_bucket_p(particles)];
+    }
+    return resolve_tuning(t, n, particles);
+}
+
+}  // namespace dpso
+
+using dpso::fail;
+using dpso::ok;
+
+extern "C" {
+
+dpso_status dpso_tuning_get(int32_t n, int32_t particles, dpso_tuning *out)
+{
+    if (!out) return fail(DPSO_E_INVAL, "out is NULL");
+    if (n < 1 || n > DPSO_MAX_N) return fail(DPSO_E_RANGE, "n = %d outside 1..DPSO_MAX_N", n);
+    if (particles < 1) return fail(DPSO_E_INVAL, "particles = %d must be at least 1", particles);
+    const dpso::Tune t = dpso::tuning_for(n, particles);
+    out->move_threads = t.move_threads;
+    out->exchange_rows = t.exchange_rows;
+    return ok();
+}
+
+dpso_status dpso_tuning_set(int32_t n, int32_t particles, const dpso_tuning *t)
+{
+    if (n < 1 || n > DPSO_MAX_N) return fail(DPSO_E_RANGE, "n = %d outside 1..DPSO_MAX_N", n);
+    if (particles < 1) return fail(DPSO_E_INVAL, "particles = %d must be at least 1", particles);
+    const int bn = dpso::tune_bucket_n(n), bp = dpso::tune_bucket_p(particles);
+    dpso::Tune e{0, 0};
+    if (t) {
+        if (t->move_threads != 0 && t->move_threads != 64 && t->move_threads != 128 && t->move_threads != 256)
+            return fail(DPSO_E_INVAL, "move_threads = %d is not 0, 64, 128 or 256", t->move_threads);
+        if (t->exchange_rows < DPSO_ROWS_AUTO || t->exchange_rows > DPSO_ROWS_BLOCK)
+            return fail(DPSO_E_INVAL, "exchange_rows = %d is not a DPSO_ROWS_* value", t->exchange_rows);
+        const int top = dpso::bucket_max_n(bn), ns = (top + 63) & ~63;
+        if (t->move_threads != 0 && !dpso::move_threads_ok(t->move_threads, ns))
+            return fail(DPSO_E_RANGE, "%d threads per particle cannot serve n = %d (at most 16 positions each)",
+                        t->move_threads, top);
+        if ((t->exchange_rows == DPSO_ROWS_U16 || t->exchange_rows == DPSO_ROWS_I32) && n > 1024)
+            return fail(DPSO_E_RANGE, "the wavefront exchange serves n up to 1024");
+        e.move_threads = t->move_threads;
+        e.exchange_rows = t->exchange_rows;
+    }
+    std::lock_guard<std::mutex> lock(dpso::g_table_mutex);
+    dpso::g_tables[dpso::current_device()].entry[bn][bp] = e;
+    return ok();
+}
+
+dpso_status dpso_tuning_reset(void)
+{
+    std::lock_guard<std::mutex> lock(dpso::g_table_mutex);
+    dpso::g_tables[dpso::current_device()] = dpso::Table{};
+    return ok();
+}
+
+dpso_status dpso_batch_order_set(int32_t order)
+{
+    if (order < DPSO_ORDER_DEFAULT || order > DPSO_ORDER_XCD)
+        return fail(DPSO_E_INVAL, "batch order %d is not a DPSO_ORDER_* value", order);
+    std::lock_guard<std::mutex> lock(dpso::g_table_mutex);
+    dpso::g_tables[dpso::current_device()].order = order;
+    return ok();
+}
+
+int32_t dpso_batch_order_get(void) { return dpso::batch_order(); }
+
+}  // extern "C"

@@ -705,7 +705,9 @@ template <int MB, bool VEC4, bool HALF>
 __global__ __launch_bounds__(64, DPSO_2OPT_WAVES) void k_2opt_wave_batch(Batch B)
 {
     int p;
-    const Inst &I = batch_pick(B, int(blockIdx.x), p);
+    const int b = batch_item(B, int(blockIdx.x));
+    if (b < 0) return;
+    const Inst &I = batch_pick(B, b, p);
     twoopt_wave_body<MB, VEC4, HALF>(I, p);
 }
 
@@ -766,7 +768,9 @@ __global__ __launch_bounds__(kThreads) void k_2opt_rows(Inst I) { twoopt_rows_bo
 __global__ __launch_bounds__(kThreads) void k_2opt_rows_batch(Batch B)
 {
     int p;
-    const Inst &I = batch_pick(B, int(blockIdx.x), p);
+    const int b = batch_item(B, int(blockIdx.x));
+    if (b < 0) return;
+    const Inst &I = batch_pick(B, b, p);
     twoopt_rows_body(I, p);
 }
 
@@ -831,19 +835,19 @@ int pack_blocks(int n) { return int(std::min<int64_t>(1024, (int64_t(n) * packed
 
 }  // namespace
 
-int exchange_class(int n, const int32_t *D, int neighbourhood)
+int exchange_class(int n, const int32_t *D, int neighbourhood, int rows)
 {
     if (neighbourhood == DPSO_NB_NODE_SWAP) return kExchangeClasses - 1;
-    if (n > 1024) return kExchangeClasses - 2;
+    if (n > 1024 || rows == DPSO_ROWS_BLOCK) return kExchangeClasses - 2;
     const int mb = n <= 64 ? 0 : n <= 128 ? 1 : n <= 256 ? 2 : n <= 512 ? 3 : 4;
-    if (kHalf && packed_rows(n)) return kFirstHalfClass + mb;
+    if (kHalf && rows == DPSO_ROWS_U16 && packed_rows(n)) return kFirstHalfClass + mb;
     const bool vec4 = (n & 3) == 0 && (reinterpret_cast<uintptr_t>(D) & 15) == 0;
     return vec4 ? mb : 5 + mb;
 }
 
-hipError_t launch_2opt_prepare(const Inst &I, hipStream_t s)
+hipError_t launch_2opt_prepare(const Inst &I, int cls, hipStream_t s)
 {
-    if (!half_class(exchange_class(I.st.n, I.D, I.kp.ee_neighbourhood))) return hipSuccess;
+    if (!half_class(cls)) return hipSuccess;
     const dim3 grid(pack_blocks(I.st.n), 1);
     k_pack_max<<<grid, kPackThreads, 0, s>>>(I);
     k_pack_rows<<<grid, kPackThreads, 0, s>>>(I);
@@ -859,9 +863,9 @@ hipError_t launch_batch_2opt_prepare(int cls, const Batch &members, int max_n, h
     return hipGetLastError();
 }
 
-hipError_t launch_2opt(const Inst &I, hipStream_t s)
+hipError_t launch_2opt(const Inst &I, int cls, hipStream_t s)
 {
-    return launch_class(exchange_class(I.st.n, I.D, I.kp.ee_neighbourhood), &I, Batch{}, I.st.S, I.st.ns, s);
+    return launch_class(cls, &I, Batch{}, I.st.S, I.st.ns, s);
 }
 
 hipError_t launch_batch_2opt(int cls, const Batch &items, int total, int max_ns, hipStream_t s)

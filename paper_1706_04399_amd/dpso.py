@@ -22,6 +22,8 @@ MAX_N = 4096
 MAX_SWARM = 65536
 EE_OFF, EE_ON_STALL, EE_ALWAYS = 0, 1, 2
 NB_TWO_OPT, NB_NODE_SWAP = 0, 1
+ROWS_AUTO, ROWS_U16, ROWS_I32, ROWS_BLOCK = 0, 1, 2, 3
+ORDER_DEFAULT, ORDER_INDEX, ORDER_LPT, ORDER_XCD = 0, 1, 2, 3
 
 
 class DpsoError(RuntimeError):
@@ -77,6 +79,14 @@ class BatchItem(C.Structure):
                 ("d_state", C.c_void_p), ("state_bytes", C.c_size_t)]
 
 
+class Tuning(C.Structure):
+    _fields_ = [("move_threads", C.c_int32), ("exchange_rows", C.c_int32)]
+
+
+class TuneResult(C.Structure):
+    _fields_ = [("config", Tuning), ("ms", C.c_float), ("digest", C.c_uint64)]
+
+
 class HostState(C.Structure):
     _fields_ = [("X", C.c_void_p), ("P", C.c_void_p), ("V", C.c_void_p), ("vlen", C.c_void_p),
                 ("F", C.c_void_p), ("FP", C.c_void_p), ("G", C.c_void_p), ("trace", C.c_void_p),
@@ -117,6 +127,14 @@ EXPORTS = {
     "dpso_voxel_work_bytes": (C.c_size_t, [C.c_void_p, C.c_void_p]),
     "dpso_build_dist_voxel": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,
                                           C.c_void_p]),
+    "dpso_tuning_get": (C.c_int32, [C.c_int32, C.c_int32, C.c_void_p]),
+    "dpso_tuning_set": (C.c_int32, [C.c_int32, C.c_int32, C.c_void_p]),
+    "dpso_tuning_reset": (C.c_int32, []),
+    "dpso_batch_order_set": (C.c_int32, [C.c_int32]),
+    "dpso_batch_order_get": (C.c_int32, []),
+    "dpso_autotune": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_size_t, C.c_int32,
+                                  C.c_void_p, C.c_size_t, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
+                                  C.c_void_p]),
 }
 
 _lib = None
@@ -373,6 +391,56 @@ def import_state(state: torch.Tensor, n: int, swarm_size: int, host: dict, strea
                    int(host["best_cost"]))
     _check(lib().dpso_import_state(_dev(state, torch.uint8), state.numel(), n, swarm_size,
                                    C.byref(hs), _stream(stream)))
+
+
+def tuning_get(n: int, particles: int) -> dict:
+    """The configuration the library uses for n among `particles` particles
+    launched together on the current device."""
+    t = Tuning()
+    _check(lib().dpso_tuning_get(int(n), int(particles), C.byref(t)))
+    return {"move_threads": t.move_threads, "exchange_rows": t.exchange_rows}
+
+
+def tuning_set(n: int, particles: int, config: dict | None):
+    """Sets (or, with None, clears) the table entry of the bucket of
+    (n, particles) on the current device."""
+    if config is None:
+        _check(lib().dpso_tuning_set(int(n), int(particles), None))
+        return
+    t = Tuning(int(config.get("move_threads", 0)), int(config.get("exchange_rows", ROWS_AUTO)))
+    _check(lib().dpso_tuning_set(int(n), int(particles), C.byref(t)))
+
+
+def tuning_reset():
+    _check(lib().dpso_tuning_reset())
+
+
+def batch_order_set(order: int):
+    """Order of the particles in batched launches on the current device
+    (ORDER_INDEX, ORDER_LPT, ORDER_XCD or ORDER_DEFAULT)."""
+    _check(lib().dpso_batch_order_set(int(order)))
+
+
+def batch_order_get() -> int:
+    return int(lib().dpso_batch_order_get())
+
+
+def autotune(D: torch.Tensor, params, state: torch.Tensor, generations: int, stream=None) -> dict:
+    """Times every candidate configuration on `generations` generations of the
+    swarm in `state` (left unchanged), records the fastest for the bucket of
+    (n, swarm_size) and returns {"chosen": config, "results": [...]}."""
+    n = D.shape[0]
+    scratch = torch.empty_like(state)
+    res = (TuneResult * 16)()
+    count = C.c_int32(0)
+    chosen = Tuning()
+    _check(lib().dpso_autotune(_dev(D, torch.int32), n, C.byref(_params(params)), _dev(state, torch.uint8),
+                               state.numel(), int(generations), _dev(scratch, torch.uint8), scratch.numel(),
+                               res, 16, C.byref(count), C.byref(chosen), _stream(stream)))
+    out = [{"move_threads": r.config.move_threads, "exchange_rows": r.config.exchange_rows,
+            "ms": float(r.ms), "digest": int(r.digest)} for r in res[: count.value]]
+    return {"chosen": {"move_threads": chosen.move_threads, "exchange_rows": chosen.exchange_rows},
+            "results": out}
 
 
 def batch_work_bytes(count: int) -> int:

@@ -32,8 +32,8 @@ ROOT = os.path.dirname(os.path.dirname(HERE))
 CSRC = os.path.join(ROOT, "paper_1706_04399_amd", "csrc")
 OUT = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libdpso_emu.so")
-SOURCES = ["api.hip", "swarm.hip", "twoopt.hip", "nodeswap.hip", "dist.hip", "checkdist.hip"]
-HEADERS = ["device.hpp", "kernels.hpp", "state.hpp", "errors.hpp"]
+SOURCES = ["api.hip", "tune.hip", "swarm.hip", "twoopt.hip", "nodeswap.hip", "dist.hip", "checkdist.hip"]
+HEADERS = ["device.hpp", "kernels.hpp", "state.hpp", "errors.hpp", "tune.hpp"]
 
 LAUNCH = re.compile(r"(?P<k>[A-Za-z_][\w:]*(?:<[^<>;()]*>)?)<<<(?P<cfg>.+?)>>>\((?P<args>.*)\);")
 
@@ -79,8 +79,30 @@ def rewrite(text: str) -> str:
     return text, n_launch
 
 
+def _up_to_date() -> bool:
+    """The library is newer than every source it is built from."""
+    if not os.path.exists(LIB):
+        return False
+    t = os.path.getmtime(LIB)
+    deps = [os.path.join(CSRC, f) for f in HEADERS + SOURCES] + [os.path.join(HERE, "emu.cpp"), __file__,
+            os.path.join(HERE, "include", "hip", "hip_runtime.h"), os.path.join(ROOT, "include", "dpso.h")]
+    return all(os.path.getmtime(d) < t for d in deps)
+
+
 def build(verbose=True) -> str:
+    """Builds the library unless it is up to date. Concurrent callers (test
+    workers) take turns on a lock file, and the library is replaced in one
+    step, so a reader never sees a partial file."""
+    import fcntl
     os.makedirs(OUT, exist_ok=True)
+    with open(os.path.join(OUT, ".lock"), "w") as lock:
+        fcntl.flock(lock, fcntl.LOCK_EX)
+        if _up_to_date():
+            return LIB
+        return _build(verbose)
+
+
+def _build(verbose) -> str:
     objs, launches = [], 0
     for name in HEADERS + SOURCES:
         text, n = rewrite(open(os.path.join(CSRC, name)).read())
@@ -92,7 +114,8 @@ def build(verbose=True) -> str:
              "-Wno-attributes", "-Wno-ignored-attributes", "-Wno-unused-result",
              "-I", os.path.join(HERE, "include"), "-I", os.path.join(ROOT, "include"), "-I", OUT]
     srcs = [os.path.join(OUT, s.replace(".hip", ".cpp")) for s in SOURCES] + [os.path.join(HERE, "emu.cpp")]
-    cmd = ["g++"] + flags + ["-shared", "-o", LIB] + srcs
+    tmp = LIB + f".tmp{os.getpid()}"
+    cmd = ["g++"] + flags + ["-shared", "-o", tmp] + srcs
     if verbose:
         print(" ".join(cmd), flush=True)
         print(f"{launches} kernel launches rewritten", flush=True)
@@ -100,6 +123,7 @@ def build(verbose=True) -> str:
     if res.returncode != 0:
         sys.stderr.write(res.stderr[-20000:])
         raise RuntimeError("host build of the emulated library failed")
+    os.replace(tmp, LIB)
     return LIB
 
 

@@ -237,6 +237,7 @@ inline uint32_t emu_add_sat(uint32_t a, uint32_t b)
 
 typedef int hipError_t;
 constexpr hipError_t hipSuccess = 0;
+constexpr hipError_t hipErrorInvalidConfiguration = 9;
 typedef void *hipStream_t;
 typedef void *hipEvent_t;
 typedef void *hipGraph_t;
@@ -265,6 +266,15 @@ inline hipError_t hipMemcpy2DAsync(void *dst, size_t dpitch, const void *src, si
 inline hipError_t hipStreamSynchronize(hipStream_t) { return hipSuccess; }
 inline hipError_t hipEventCreate(hipEvent_t *e) { *e = nullptr; return hipSuccess; }
 inline hipError_t hipEventRecord(hipEvent_t, hipStream_t) { return hipSuccess; }
+inline hipError_t hipEventSynchronize(hipEvent_t) { return hipSuccess; }
+// streams and events: every launch runs to completion when it is made, so
+// ordering between streams holds by construction
+constexpr unsigned hipStreamNonBlocking = 1;
+constexpr unsigned hipEventDisableTiming = 2;
+inline hipError_t hipStreamCreateWithFlags(hipStream_t *s, unsigned) { *s = nullptr; return hipSuccess; }
+inline hipError_t hipEventCreateWithFlags(hipEvent_t *e, unsigned) { *e = nullptr; return hipSuccess; }
+inline hipError_t hipEventDestroy(hipEvent_t) { return hipSuccess; }
+inline hipError_t hipStreamWaitEvent(hipStream_t, hipEvent_t, unsigned) { return hipSuccess; }
 inline hipError_t hipEventElapsedTime(float *ms, hipEvent_t, hipEvent_t) { *ms = 0.f; return hipSuccess; }
 inline hipError_t hipStreamIsCapturing(hipStream_t, hipStreamCaptureStatus *c)
 {

@@ -220,6 +220,147 @@ def case_batch(emu: Emu) -> bool:
     return ok
 
 
+class Tuning(C.Structure):
+    _fields_ = [("move_threads", C.c_int32), ("exchange_rows", C.c_int32)]
+
+
+class TuneResult(C.Structure):
+    _fields_ = [("config", Tuning), ("ms", C.c_float), ("digest", C.c_uint64)]
+
+
+# forced configurations: (threads per particle in the move, exchange rows:
+# 1 16-bit, 2 int32, 3 one workgroup per particle); a field a bucket cannot
+# take is left to the default there
+TUNINGS = [(64, 1), (128, 2), (256, 3), (64, 3), (128, 1), (64, 2)]
+
+
+def force_tuning(emu: Emu, tpb: int, rows: int):
+    """Sets every bucket of the table to (tpb, rows) where it can serve it."""
+    L = emu.L
+    L.dpso_tuning_reset()
+    for b in range(1, 13):
+        n = min(1 << b, 4096)
+        for particles in (100, 500, 1000, 2000, 5000, 10000):
+            for t in ((tpb, rows), (tpb, 0), (0, rows)):
+                if L.dpso_tuning_set(n, particles, C.byref(Tuning(*t))) == 0:
+                    break
+
+
+def case_tuned(emu: Emu, full: bool) -> bool:
+    """The batch of every class and single swarms under each forced
+    configuration: results equal to the oracle's whatever the table. Without
+    `full`, the first three tables, the batch's instances up to n = 131 and
+    two single swarms."""
+    ok = True
+    gens = 3
+    refs_cache = {}
+    batch = BATCH if full else [c for c in BATCH if c[0] <= 131]
+    for tpb, rows in (TUNINGS if full else TUNINGS[:3]):
+        force_tuning(emu, tpb, rows)
+        members, refs = _batch_members(emu, batch, gens)
+        emu.init_batch(members)
+        emu.run_batch(members, gens)
+        for k, ((D, n, prm, st), (Dref, _)) in enumerate(zip(members, refs)):
+            if k not in refs_cache:
+                ref = oracle.new_state(Dref, prm)
+                oracle.run(Dref, prm, ref, gens)
+                refs_cache[k] = ref
+            ok &= compare(f"tuning {tpb}/{rows} batch n={n} S={prm['swarm_size']}",
+                          emu.export(st, n, prm["swarm_size"]), refs_cache[k])
+            emu.free(D)
+            emu.free(st[0])
+        # a single swarm whose n is in no other bucket of the batch
+        for n in ((12, 200, 700) if full else (12, 100)):
+            sc = scenes.random_points(n, seed=7, n_boxes=2)
+            Dref = oracle.build_dist(sc)
+            D = emu.alloc(4 * n * n)
+            C.memmove(D, np.ascontiguousarray(Dref).ctypes.data, 4 * n * n)
+            prm = scenes.swarm_params(3, gens, seed=1, instance=2, ee_trigger=2)
+            st = emu.new_state(n, prm)
+            emu.init_nn(D, n, prm, st)
+            emu.run(D, n, prm, st, gens)
+            ref = oracle.new_state(Dref, prm)
+            oracle.run(Dref, prm, ref, gens)
+            ok &= compare(f"tuning {tpb}/{rows} single n={n}", emu.export(st, n, 3), ref)
+            emu.free(D)
+            emu.free(st[0])
+    emu.L.dpso_tuning_reset()
+    return ok
+
+
+def case_autotune(emu: Emu) -> bool:
+    """dpso_autotune on a small swarm: every candidate's digest agrees, the
+    state is left as it was, the pick lands in the table and a run after it
+    still equals the oracle."""
+    ok = True
+    n, gens = 90, 2
+    sc = scenes.random_points(n, seed=3, n_boxes=2)
+    Dref = oracle.build_dist(sc)
+    D = emu.alloc(4 * n * n)
+    C.memmove(D, np.ascontiguousarray(Dref).ctypes.data, 4 * n * n)
+    prm = scenes.swarm_params(4, 6, seed=2, instance=1, ee_trigger=2)
+    st = emu.new_state(n, prm)
+    emu.init_nn(D, n, prm, st)
+    emu.run(D, n, prm, st, 1)
+    before = emu.export(st, n, 4)
+    scratch = emu.alloc(st[1])
+    res = (TuneResult * 16)()
+    count, chosen = C.c_int32(0), Tuning()
+    p = params(prm)
+    status = emu.L.dpso_autotune(C.c_void_p(D), n, C.byref(p), C.c_void_p(st[0]), C.c_size_t(st[1]), gens,
+                                 C.c_void_p(scratch), C.c_size_t(st[1]), res, 16, C.byref(count),
+                                 C.byref(chosen), None)
+    if status != 0:
+        print("autotune failed:", emu.L.dpso_last_error().decode(), flush=True)
+        return False
+    digests = {res[k].digest for k in range(count.value)}
+    cfgs = [(res[k].config.move_threads, res[k].config.exchange_rows) for k in range(count.value)]
+    print(f"autotune: {count.value} candidates {cfgs}, {len(digests)} digest(s), chosen "
+          f"{(chosen.move_threads, chosen.exchange_rows)}", flush=True)
+    ok &= len(digests) == 1 and count.value >= 4
+    after = emu.export(st, n, 4)
+    same = all(np.array_equal(np.asarray(before[k]), np.asarray(after[k])) for k in before)
+    print(f"autotune leaves the state unchanged: {same}", flush=True)
+    ok &= same
+    got = Tuning()
+    emu.L.dpso_tuning_get(n, 4, C.byref(got))
+    ok &= (got.move_threads, got.exchange_rows) == (chosen.move_threads, chosen.exchange_rows)
+    emu.run(D, n, prm, st, 2)
+    ref = oracle.new_state(Dref, prm)
+    oracle.run(Dref, prm, ref, 3)
+    ok &= compare(f"run after autotune n={n}", emu.export(st, n, 4), ref)
+    emu.L.dpso_tuning_reset()
+    return ok
+
+
+def case_orders(emu: Emu) -> bool:
+    """A batch whose classes have 8 or more members (16 instances of n = 50,
+    eight of n = 97, one move class and two exchange classes) in
+    each batch order: index, longest first, and XCD groups (balanced here, so
+    every launch is grouped and blocks past a group's end do nothing)."""
+    ok = True
+    gens = 3
+    cases = [(50, 6, dict(ee_trigger=2))] * 16 + [(97, 4, dict(ee_trigger=2))] * 8
+    refs = None
+    for order in (1, 2, 3):
+        emu.L.dpso_batch_order_set(order)
+        members, rr = _batch_members(emu, cases, gens)
+        if refs is None:
+            refs = []
+            for (D, n, prm, st), (Dref, _) in zip(members, rr):
+                ref = oracle.new_state(Dref, prm)
+                oracle.run(Dref, prm, ref, gens)
+                refs.append(ref)
+        emu.init_batch(members)
+        emu.run_batch(members, gens)
+        for k, ((D, n, prm, st), ref) in enumerate(zip(members, refs)):
+            ok &= compare(f"order {order} instance {k} n={n}", emu.export(st, n, prm["swarm_size"]), ref)
+            emu.free(D)
+            emu.free(st[0])
+    emu.L.dpso_batch_order_set(0)
+    return ok
+
+
 def case_plain(emu: Emu, count: int) -> bool:
     """The batched workload's instances (n log-uniform in [20, 500]) solved
     one after another on the single-instance path, swarm 8, 6 generations."""
@@ -307,6 +448,12 @@ def main(argv):
         ok = case_quick(emu)
     elif case == "batch":
         ok = case_batch(emu)
+    elif case == "tuned":
+        ok = case_tuned(emu, len(argv) > 1 and argv[1] == "full")
+    elif case == "orders":
+        ok = case_orders(emu)
+    elif case == "autotune":
+        ok = case_autotune(emu)
     elif case == "plain":
         ok = case_plain(emu, int(argv[1]) if len(argv) > 1 else 24)
     elif case == "serve":

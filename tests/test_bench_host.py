@@ -19,16 +19,23 @@ def test_more_than_one_gpu_is_refused():
 
 
 @pytest.mark.parametrize("n,name", [
-    (1000, "k_2opt_wave<16, true, true>"),    # 16-bit rows (n > 256)
+    (1000, "k_2opt_wave<16, true, true>"),    # 16-bit rows (n > 512)
     (1024, "k_2opt_wave<16, true, true>"),
     (1021, "k_2opt_wave<16, true, true>"),    # padded 16-bit rows
-    (260, "k_2opt_wave<8, true, true>"),
-    (256, "k_2opt_wave<4, true, false>"),     # int32 rows straight into LDS
+    (516, "k_2opt_wave<16, true, true>"),
+    (512, "k_2opt_wave<8, true, false>"),     # int32 rows straight into LDS (n <= 512, n % 4 == 0)
+    (260, "k_2opt_wave<8, true, false>"),
+    (256, "k_2opt_wave<4, true, false>"),
     (255, "k_2opt_wave<4, true, true>"),      # rows of D off 16 bytes: 16-bit copy
     (64, "k_2opt_wave<1, true, false>"),
     (9, "k_2opt_wave<1, true, true>"),
     (5, "k_2opt_wave<1, false, false>"),      # below 8: int32 rows through registers
     (1025, "k_2opt_rows"),
 ])
-def test_exchange_kernel_name_follows_the_row_policy(n, name):
-    assert bench.exchange_kernel_name(n) == name
+def test_exchange_kernel_name_follows_the_default_rows(n, name):
+    """The kernel bench.py names for the library's default row form of n
+    (the tuning table is read on the host; no GPU)."""
+    from paper_1706_04399_amd import dpso
+    dpso.tuning_reset()
+    rows = dpso.tuning_get(n, 4096)["exchange_rows"]
+    assert bench.exchange_kernel_name(n, rows) == name

@@ -54,3 +54,20 @@ ORDERS = os.environ.get("EMU_ORDERS", "fwd").split(",")
 def test_batch_of_every_class_matches_oracle_under_sanitizers(emu_lib, order):
     """Every edge-exchange class and variant in one batch."""
     _run("batch", order)
+
+
+def test_every_tuning_matches_oracle_under_sanitizers(emu_lib):
+    """Batches and single swarms under six forced tuning tables (threads per
+    particle in the move x the exchange's row form)."""
+    _run("tuned")
+
+
+def test_autotune_under_sanitizers(emu_lib):
+    """The autotuner's candidates agree, the swarm is left as it was and the
+    pick lands in the table."""
+    _run("autotune")
+
+
+def test_batch_orders_under_sanitizers(emu_lib):
+    """Index order, longest-first order and XCD groups give the oracle's swarms."""
+    _run("orders")

@@ -96,10 +96,108 @@ def test_state_bytes(dp):
     assert 4096 * 1024 * 8 + 2 * 1000 * 1000 <= a < 4096 * 1024 * 8 + 2 * 1000 * 1000 + (1 << 20)
     b = dp.state_bytes(1001, 4096, 2000)
     assert 4096 * 1024 * 8 + 2 * 1001 * 1008 <= b < 4096 * 1024 * 8 + 2 * 1001 * 1008 + (1 << 20)
-    c = dp.state_bytes(256, 64, 10)   # int32 rows of D staged directly: no copy
-    assert c < 64 * 256 * 8 + (1 << 16)
-    d = dp.state_bytes(255, 64, 10)   # rows of D not on 16 bytes: a padded 16-bit copy
+    # every 8 <= n <= 1024 holds the 16-bit copy (the tuning table may pick
+    # 16-bit rows for any of them); n below 8 and above 1024 hold none
+    c = dp.state_bytes(256, 64, 10)
+    assert 64 * 256 * 8 + 256 * 256 * 2 <= c < 64 * 256 * 8 + 256 * 256 * 2 + (1 << 16)
+    d = dp.state_bytes(255, 64, 10)
     assert d >= 255 * 256 * 2
+    assert dp.state_bytes(7, 64, 10) < 64 * 64 * 8 + (1 << 16)
+    assert dp.state_bytes(1025, 8, 10) < 8 * 1088 * 8 + (1 << 16)
+
+
+def test_tuning_table(dp):
+    """Buckets, defaults, validation and reset of the per-device table (host only)."""
+    dp.tuning_reset()
+    # defaults: one wavefront per particle in the move for a lone small swarm
+    # and for n <= 512 among more than 2048 particles, else 256 threads; int32
+    # rows for n <= 512 a multiple of 4 (and below n = 8, where no 16-bit copy
+    # exists), 16-bit rows for other n up to 1024, one workgroup per particle
+    # above
+    assert dp.tuning_get(1000, 4096) == {"move_threads": 256, "exchange_rows": dp.ROWS_U16}
+    assert dp.tuning_get(30, 64) == {"move_threads": 64, "exchange_rows": dp.ROWS_U16}
+    assert dp.tuning_get(200, 1024) == {"move_threads": 256, "exchange_rows": dp.ROWS_I32}
+    assert dp.tuning_get(200, 65536) == {"move_threads": 64, "exchange_rows": dp.ROWS_I32}
+    assert dp.tuning_get(384, 4096) == {"move_threads": 64, "exchange_rows": dp.ROWS_I32}
+    assert dp.tuning_get(385, 4096) == {"move_threads": 64, "exchange_rows": dp.ROWS_U16}
+    assert dp.tuning_get(516, 4096) == {"move_threads": 256, "exchange_rows": dp.ROWS_U16}
+    assert dp.tuning_get(2000, 8) == {"move_threads": 256, "exchange_rows": dp.ROWS_BLOCK}
+    assert dp.tuning_get(2000, 64)["move_threads"] == 256     # 64 threads serve n <= 1024 only
+    assert dp.tuning_get(5, 8)["exchange_rows"] == dp.ROWS_I32
+    try:
+        dp.tuning_set(200, 1024, {"move_threads": 128, "exchange_rows": dp.ROWS_U16})
+        # the whole bucket: n in (128, 256], 513 .. 1024 particles launched together
+        assert dp.tuning_get(129, 513) == {"move_threads": 128, "exchange_rows": dp.ROWS_U16}
+        assert dp.tuning_get(256, 1024) == {"move_threads": 128, "exchange_rows": dp.ROWS_U16}
+        assert dp.tuning_get(128, 1024)["move_threads"] == 256
+        assert dp.tuning_get(200, 1025)["move_threads"] == 256
+        assert dp.tuning_get(200, 2049)["move_threads"] == 64
+        assert dp.tuning_get(200, 512)["move_threads"] == 256
+        # int32 rows for an n off 16 bytes resolve to 16-bit rows
+        dp.tuning_set(200, 1024, {"exchange_rows": dp.ROWS_I32})
+        assert dp.tuning_get(200, 1024)["exchange_rows"] == dp.ROWS_I32
+        assert dp.tuning_get(201, 1024)["exchange_rows"] == dp.ROWS_U16
+        # a partial entry: the other field keeps its default
+        dp.tuning_set(30, 64, {"move_threads": 128})
+        assert dp.tuning_get(30, 64) == {"move_threads": 128, "exchange_rows": dp.ROWS_U16}
+        dp.tuning_set(200, 1024, None)
+        assert dp.tuning_get(200, 1024) == {"move_threads": 256, "exchange_rows": dp.ROWS_I32}
+        # 64 threads serve n up to 1024, 128 up to 2048; the wavefront exchange n up to 1024
+        dp.tuning_set(1024, 64, {"move_threads": 64})
+        for n, cfg in ((1025, {"move_threads": 64}), (2049, {"move_threads": 128}),
+                       (1500, {"exchange_rows": dp.ROWS_U16}), (1500, {"exchange_rows": dp.ROWS_I32})):
+            with pytest.raises(dp.DpsoError) as e:
+                dp.tuning_set(n, 64, cfg)
+            assert e.value.status == dp.E_RANGE, (n, cfg)
+        for cfg in ({"move_threads": 32}, {"move_threads": 512}, {"exchange_rows": 4}, {"exchange_rows": -1}):
+            with pytest.raises(dp.DpsoError) as e:
+                dp.tuning_set(100, 64, cfg)
+            assert e.value.status == dp.E_INVAL, cfg
+        for bad in ((0, 64), (dp.MAX_N + 1, 64)):
+            with pytest.raises(dp.DpsoError):
+                dp.tuning_get(*bad)
+        with pytest.raises(dp.DpsoError):
+            dp.tuning_get(100, 0)
+        # a 16-bit entry over a bucket whose smallest n has no 16-bit copy
+        dp.tuning_set(6, 64, {"exchange_rows": dp.ROWS_U16})
+        assert dp.tuning_get(8, 64)["exchange_rows"] == dp.ROWS_U16
+        assert dp.tuning_get(7, 64)["exchange_rows"] == dp.ROWS_I32
+        # the batch order
+        assert dp.batch_order_get() == dp.ORDER_LPT
+        for o in (dp.ORDER_INDEX, dp.ORDER_XCD, dp.ORDER_LPT):
+            dp.batch_order_set(o)
+            assert dp.batch_order_get() == o
+        dp.batch_order_set(dp.ORDER_XCD)
+        for bad in (-1, 4):
+            with pytest.raises(dp.DpsoError) as e:
+                dp.batch_order_set(bad)
+            assert e.value.status == dp.E_INVAL
+    finally:
+        dp.tuning_reset()
+    assert dp.tuning_get(1024, 64)["move_threads"] == 64
+    assert dp.batch_order_get() == dp.ORDER_LPT
+
+
+def test_autotune_validation(dp):
+    """Argument checks that fail before any device work."""
+    import ctypes as C
+    p = dp._params(_params())
+    lib = dp.lib()
+    res = (dp.TuneResult * 4)()
+    cnt, ch = C.c_int32(), dp.Tuning()
+    fake = C.c_void_p(0x1000)
+    need = dp.state_bytes(30, p.swarm_size, p.max_generations)
+    cases = [
+        ((None, 30, C.byref(p), fake, need, 3, fake, need, res, 4, C.byref(cnt), C.byref(ch), None), dp.E_INVAL),
+        ((fake, 30, C.byref(p), fake, need, 0, fake, need, res, 4, C.byref(cnt), C.byref(ch), None), dp.E_INVAL),
+        ((fake, 30, C.byref(p), fake, need, 3, fake, need - 1, res, 4, C.byref(cnt), C.byref(ch), None), dp.E_NOMEM),
+        ((fake, 30, C.byref(p), fake, need - 1, 3, fake, need, res, 4, C.byref(cnt), C.byref(ch), None), dp.E_NOMEM),
+        ((fake, 30, C.byref(p), fake, need, 3, None, need, res, 4, C.byref(cnt), C.byref(ch), None), dp.E_INVAL),
+        ((fake, 30, C.byref(p), fake, need, 3, fake, need, None, 4, C.byref(cnt), C.byref(ch), None), dp.E_INVAL),
+        ((fake, 0, C.byref(p), fake, need, 3, fake, need, res, 4, C.byref(cnt), C.byref(ch), None), dp.E_INVAL),
+    ]
+    for args, code in cases:
+        assert lib.dpso_autotune(*args) == code, args
 
 
 def test_calls_reject_null_pointers_before_device_work(dp):
