@@ -480,31 +480,36 @@ hipError_t fan_out(const ClassPlan *cls, int classes, Fan *f, FanEvents *ev, hip
     return e;
 }
 
-// All launches of `generations` generations of a batch; the move and
-// exchange classes fan out when `f` is given.
-hipError_t enqueue_batch(const BatchPlan &P, int32_t generations, hipStream_t s, Fan *f = nullptr,
-                         FanEvents *ev = nullptr)
+// The launches that open a batched run: the state check and, for classes
+// that stage 16-bit rows, the packing of each member's copy of D.
+hipError_t enqueue_batch_prologue(const BatchPlan &P, hipStream_t s)
 {
     hipError_t e = dpso::launch_batch_check(P.items, P.instances, P.total, P.max_ns, s);
     for (int c = 0; c < dpso::kExchangeClasses && e == hipSuccess && P.any_exchange; ++c)
         e = dpso::launch_batch_2opt_prepare(c, P.cls[c].members, P.cls[c].max_ns, s);
+    return e;
+}
+
+// The launches of one generation of a batch; the move and exchange classes
+// fan out when `f` is given. Every kernel reads the generation counter and
+// the stop flags from the states, so the same launches serve every
+// generation.
+hipError_t enqueue_batch_generation(const BatchPlan &P, hipStream_t s, Fan *f = nullptr, FanEvents *ev = nullptr)
+{
     auto move = [&](int c, hipStream_t st) {
         return dpso::launch_batch_move(move_class_threads(c), P.mv[c].members, P.mv[c].grid, P.mv[c].max_ns, st);
     };
     auto exchange = [&](int c, hipStream_t st) {
         return dpso::launch_batch_2opt(c, P.cls[c].members, P.cls[c].grid, P.cls[c].max_ns, st);
     };
-    for (int32_t g = 0; g < generations && e == hipSuccess; ++g) {
-        e = fan_out(P.mv, kMoveClasses, f, ev, s, move);
-        if (e == hipSuccess && P.any_mutation)
-            e = dpso::launch_batch_mutation(P.items, P.instances, P.total, P.max_ns, s);
-        if (e == hipSuccess) e = dpso::launch_batch_gbest(P.items, P.instances, P.total, P.max_ns, 1, s);
-        if (P.any_exchange) {
-            if (e == hipSuccess) e = fan_out(P.cls, dpso::kExchangeClasses, f, ev, s, exchange);
-            if (e == hipSuccess) e = dpso::launch_batch_gbest(P.items, P.instances, P.total, P.max_ns, 3, s);
-        } else if (e == hipSuccess) {
-            e = dpso::launch_batch_end(P.items, P.instances, P.total, P.max_ns, s);
-        }
+    hipError_t e = fan_out(P.mv, kMoveClasses, f, ev, s, move);
+    if (e == hipSuccess && P.any_mutation) e = dpso::launch_batch_mutation(P.items, P.instances, P.total, P.max_ns, s);
+    if (e == hipSuccess) e = dpso::launch_batch_gbest(P.items, P.instances, P.total, P.max_ns, 1, s);
+    if (P.any_exchange) {
+        if (e == hipSuccess) e = fan_out(P.cls, dpso::kExchangeClasses, f, ev, s, exchange);
+        if (e == hipSuccess) e = dpso::launch_batch_gbest(P.items, P.instances, P.total, P.max_ns, 3, s);
+    } else if (e == hipSuccess) {
+        e = dpso::launch_batch_end(P.items, P.instances, P.total, P.max_ns, s);
     }
     return e;
 }
@@ -1130,24 +1135,29 @@ dpso_status dpso_run_batch(const dpso_batch_item *items, int32_t count, int32_t 
     std::lock_guard<std::mutex> hold(fan.lock);
     FanEvents ev;
     HIP_TRY(fan_setup(fan, ev), "fan-out streams");
-    // the whole run as one graph when the stream can be captured
+    // on a stream that can be captured, one generation becomes a graph,
+    // instantiated once and launched `generations` times
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     const bool graph = s != nullptr && hipStreamIsCapturing(s, &cap) == hipSuccess &&
                        cap == hipStreamCaptureStatusNone && generations > 0;
-    if (graph) HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "begin capture");
-    hipError_t e = enqueue_batch(plan, generations, s, &fan, &ev);
-    if (graph) {
+    hipError_t e = enqueue_batch_prologue(plan, s);
+    if (graph && e == hipSuccess) {
         hipGraph_t g = nullptr;
-        const hipError_t ec = hipStreamEndCapture(s, &g);
-        if (e == hipSuccess) e = ec;
         hipGraphExec_t x = nullptr;
+        e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            e = enqueue_batch_generation(plan, s, &fan, &ev);
+            const hipError_t ec = hipStreamEndCapture(s, &g);
+            if (e == hipSuccess) e = ec;
+        }
         if (e == hipSuccess) e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
-        if (e == hipSuccess) e = hipGraphLaunch(x, s);
+        for (int32_t k = 0; k < generations && e == hipSuccess; ++k) e = hipGraphLaunch(x, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (x) hipGraphExecDestroy(x);
         if (g) hipGraphDestroy(g);
-    } else if (e == hipSuccess) {
-        e = hipStreamSynchronize(s);
+    } else {
+        for (int32_t k = 0; k < generations && e == hipSuccess; ++k) e = enqueue_batch_generation(plan, s, &fan, &ev);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
     }
     if (e != hipSuccess) return hip_fail(e, "batched run");
     return ok();

@@ -167,3 +167,30 @@ def test_autotune_refuses_a_run_past_max_generations(dp):
     with pytest.raises(dp.DpsoError) as e:
         dp.autotune(Dg, prm, state, 3)
     assert e.value.status == dp.E_RANGE
+
+
+def test_batch_graph_replays_match_oracle(dp):
+    """dpso_run_batch on a capturable stream replays one captured generation:
+    three calls of three replays each, with the program's own work and a
+    synchronisation between calls, every call's states against the oracle at
+    the same generation."""
+    import torch
+    members, refs = [], []
+    for k, (n, S, kw) in enumerate(BATCH[:9]):
+        sc = scenes.random_points(n, seed=500 + k, n_boxes=2 if n > 3 else 0)
+        D = oracle.build_dist(sc)
+        prm = scenes.swarm_params(S, 12, seed=k, instance=k, **kw)
+        members.append((D, prm))
+        refs.append(oracle.new_state(D, prm))
+    dp.tuning_reset()
+    stream = torch.cuda.Stream()
+    b = dp.Batch([(_dev(D), p) for D, p in members], stream=stream).init()
+    for call in range(3):
+        note(f"batch graph replays, call {call}")
+        b.run(3)
+        stream.synchronize()
+        torch.zeros(1 << 20, device="cuda").sum().item()   # other work between the calls
+        for k, ((D, prm), st, ref) in enumerate(zip(members, b.states, refs)):
+            oracle.run(D, prm, ref, 3)
+            bad = mismatches(dp.export_state(st, D.shape[0], prm["swarm_size"], stream), ref)
+            assert not bad, f"call {call} instance {k} (n={D.shape[0]}): {bad}"
