@@ -340,6 +340,54 @@ ABLATION = [
 ]
 
 
+# The same augmentations from random starts: the nearest-neighbour seeds of
+# the synthetic scenes are so strong that the swarm moves at phi = 0.4 never
+# improve on them, and every seeded variant then ends on the exchange's local
+# optimum of the seed; from random tours the mutation, the exchange and the
+# velocity and mutation variants act on the swarm itself.
+ABLATION_RANDOM = [
+    ("DPSO (random init, no mutation, no exchange)", dict(det_permille=0, mutation_period=0, ee_trigger=0)),
+    ("+ random mutation", dict(det_permille=0, ee_trigger=0)),
+    ("+ 2-opt edge exchange, no mutation", dict(det_permille=0, mutation_period=0)),
+    ("+ random mutation + 2-opt edge exchange", dict(det_permille=0)),
+    ("+ random mutation + node-swap exchange", dict(det_permille=0, ee_neighbourhood=1)),
+    ("mutation by disturbance + 2-opt exchange", dict(det_permille=0, mutation_swaps=-1)),
+    ("raw concatenated velocity + mutation + 2-opt", dict(det_permille=0, velocity_cap=-1)),
+]
+
+
+def _ablation_rows(dpso, scenes, np, torch, stream, sc, D, k, variants, trials, generations):
+    """One table of the ablation: every variant's trials as one batch."""
+    rows = []
+    for name, kw in variants:
+        kw = dict(kw)
+        if kw.get("mutation_swaps") == -1:
+            kw["mutation_swaps"] = max(2, sc.n // 10)
+        if kw.get("velocity_cap") == -1:
+            kw["velocity_cap"] = sc.n
+        prm = [scenes.swarm_params(100, generations, w=1.0, phi1=0.4, phi2=0.4, seed=s,
+                                   instance=k, **kw) for s in range(trials)]
+        b = dpso.Batch([(D, p) for p in prm], stream=stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.init().run(generations)
+        stream.synchronize()
+        dt = time.perf_counter() - t0
+        costs, reach = [], []
+        for i in range(trials):
+            _, cost, _, trace = b.best(i)
+            costs.append(cost)
+            reach.append(int(np.argmax(trace == cost)))
+        rows.append({"variant": name, "cost_mean": round(float(np.mean(costs)), 1),
+                     "cost_std": round(float(np.std(costs)), 1),
+                     "reached_at_generation_mean": round(float(np.mean(reach)), 1),
+                     "seconds_for_all_trials": round(dt, 3), "params": kw})
+    base = rows[0]["cost_mean"]
+    for r in rows:
+        r["cost_improvement_vs_dpso_pct"] = round(100.0 * (base - r["cost_mean"]) / base, 2)
+    return rows
+
+
 def bench_ablation(trials: int, generations: int):
     """Effect of each augmentation, and enhanced vs conventional DPSO, on the
     two synthetic stand-ins for the paper's datasets (facade n=30, bridge
@@ -347,7 +395,8 @@ def bench_ablation(trials: int, generations: int):
     0.4, 100 particles, mutation every 3 generations, edge exchange when the
     global best did not improve). Each variant runs `trials` seeds as one
     batch; reported: final cost mean and std, the generation at which the
-    best cost was first reached, and the batch's wall time. Also times the
+    best cost was first reached, and the batch's wall time. A second table
+    starts every variant from random tours (ABLATION_RANDOM). Also times the
     n=1000 benchmark workload with the node-swap neighbourhood against 2-opt."""
     import numpy as np
     import torch
@@ -365,34 +414,10 @@ def bench_ablation(trials: int, generations: int):
     for k, label in ((1, "building stand-in: facade n=30"), (2, "bridge stand-in: girder n=200")):
         sc, _ = scenes.workload(k)
         D = dpso.build_dist(sc)
-        rows = []
-        for name, kw in ABLATION:
-            kw = dict(kw)
-            if kw.get("mutation_swaps") == -1:
-                kw["mutation_swaps"] = max(2, sc.n // 10)
-            if kw.get("velocity_cap") == -1:
-                kw["velocity_cap"] = sc.n
-            prm = [scenes.swarm_params(100, generations, w=1.0, phi1=0.4, phi2=0.4, seed=s,
-                                       instance=k, **kw) for s in range(trials)]
-            b = dpso.Batch([(D, p) for p in prm], stream=stream)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            b.init().run(generations)
-            stream.synchronize()
-            dt = time.perf_counter() - t0
-            costs, reach = [], []
-            for i in range(trials):
-                _, cost, _, trace = b.best(i)
-                costs.append(cost)
-                reach.append(int(np.argmax(trace == cost)))
-            rows.append({"variant": name, "cost_mean": round(float(np.mean(costs)), 1),
-                         "cost_std": round(float(np.std(costs)), 1),
-                         "reached_at_generation_mean": round(float(np.mean(reach)), 1),
-                         "seconds_for_all_trials": round(dt, 3), "params": kw})
-        base = rows[0]["cost_mean"]
-        for r in rows:
-            r["cost_improvement_vs_dpso_pct"] = round(100.0 * (base - r["cost_mean"]) / base, 2)
-        out["scenes"].append({"scene": label, "n": sc.n, "rows": rows})
+        entry = {"scene": label, "n": sc.n}
+        for key, variants in (("rows", ABLATION), ("rows_random_start", ABLATION_RANDOM)):
+            entry[key] = _ablation_rows(dpso, scenes, np, torch, stream, sc, D, k, variants, trials, generations)
+        out["scenes"].append(entry)
     # throughput of the two neighbourhoods on the benchmark workload
     sc, prm3 = scenes.workload(3)
     D = dpso.build_dist(sc)
