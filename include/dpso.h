@@ -347,13 +347,11 @@ dpso_status dpso_init_batch(const dpso_batch_item *items, int32_t count, void *d
 
 /* dpso_run for many independent swarms: every generation is one launch per
  * phase covering all instances' particles (one per move class and one per
- * edge-exchange class, the classes of a phase on parallel streams, ordered
- * by dpso_batch_order_get), so each phase boundary synchronises the whole
- * batch and the hardware scheduler balances instances of uneven size. On a
- * non-null stream that is not already capturing, one generation is captured
- * into a hipGraph (the classes as parallel branches), instantiated once and
- * launched `generations` times. Each instance's result is identical to
- * dpso_run on it alone. Calls on one device are serialised. Synchronises
+ * edge-exchange class, ordered by dpso_batch_order_get), so each kernel
+ * boundary synchronises the whole batch and the hardware scheduler balances
+ * instances of uneven size. On a non-null stream that is not already
+ * capturing, the whole run is captured into one hipGraph and launched once.
+ * Each instance's result is identical to dpso_run on it alone. Synchronises
  * `stream`. */
 dpso_status dpso_run_batch(const dpso_batch_item *items, int32_t count, int32_t generations,
                            void *d_work, size_t work_bytes, void *stream);

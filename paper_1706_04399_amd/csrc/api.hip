@@ -403,113 +403,30 @@ dpso_status plan_batch(const dpso_batch_item *items, int32_t count, void *d_work
     return DPSO_OK;
 }
 
-// Fan-out of a phase's independent launches (one per move class, one per
-// exchange class): each goes to one of kFan library streams that wait for
-// `s` at a fork event, and `s` waits for all of them at join events. Under
-// stream capture the launches become parallel branches of the graph, so
-// classes overlap on the GPU instead of each waiting for the previous one's
-// last blocks. The streams are created once per device (non-blocking, default
-// priority); a device's fan is used by one call at a time (`lock`).
-constexpr int kFan = 8;
-
-struct Fan {
-    std::mutex lock;
-    bool ready = false;
-    hipStream_t st[kFan] = {};
-};
-
-Fan g_fans[64];
-
-struct FanEvents {
-    hipEvent_t fork = nullptr, join[kFan] = {};
-    ~FanEvents()
-    {
-        if (fork) (void)hipEventDestroy(fork);
-        for (hipEvent_t e : join)
-            if (e) (void)hipEventDestroy(e);
-    }
-};
-
-hipError_t fan_setup(Fan &f, FanEvents &ev)
-{
-    if (!f.ready) {
-        for (int k = 0; k < kFan; ++k) {
-            hipError_t e = hipStreamCreateWithFlags(&f.st[k], hipStreamNonBlocking);
-            if (e != hipSuccess) return e;
-        }
-        f.ready = true;
-    }
-    hipError_t e = hipEventCreateWithFlags(&ev.fork, hipEventDisableTiming);
-    for (int k = 0; k < kFan && e == hipSuccess; ++k) e = hipEventCreateWithFlags(&ev.join[k], hipEventDisableTiming);
-    return e;
-}
-
-// Launches launch(c, stream) for every class c in [0, classes) with members,
-// spread over the fan when more than one has members.
-template <class Launch>
-hipError_t fan_out(const ClassPlan *cls, int classes, Fan *f, FanEvents *ev, hipStream_t s, Launch launch)
-{
-    int used = 0;
-    for (int c = 0; c < classes; ++c) used += cls[c].members.count > 0;
-    if (used == 0) return hipSuccess;
-    if (used == 1 || !f) {
-        for (int c = 0; c < classes; ++c)
-            if (cls[c].members.count > 0) {
-                hipError_t e = launch(c, s);
-                if (e != hipSuccess) return e;
-            }
-        return hipSuccess;
-    }
-    hipError_t e = hipEventRecord(ev->fork, s);
-    bool waited[kFan] = {};
-    int k = 0;
-    for (int c = 0; c < classes && e == hipSuccess; ++c) {
-        if (cls[c].members.count == 0) continue;
-        const int j = k++ % kFan;
-        if (!waited[j]) {
-            e = hipStreamWaitEvent(f->st[j], ev->fork, 0);
-            waited[j] = true;
-        }
-        if (e == hipSuccess) e = launch(c, f->st[j]);
-    }
-    for (int j = 0; j < kFan && e == hipSuccess; ++j) {
-        if (!waited[j]) continue;
-        e = hipEventRecord(ev->join[j], f->st[j]);
-        if (e == hipSuccess) e = hipStreamWaitEvent(s, ev->join[j], 0);
-    }
-    return e;
-}
-
-// The launches that open a batched run: the state check and, for classes
-// that stage 16-bit rows, the packing of each member's copy of D.
-hipError_t enqueue_batch_prologue(const BatchPlan &P, hipStream_t s)
+// All launches of `generations` generations of a batch: per generation, one
+// move launch per move class, the mutation, the first global best, one
+// exchange launch per exchange class and the second global best (with the
+// end of the generation), one after another on `s`.
+hipError_t enqueue_batch(const BatchPlan &P, int32_t generations, hipStream_t s)
 {
     hipError_t e = dpso::launch_batch_check(P.items, P.instances, P.total, P.max_ns, s);
     for (int c = 0; c < dpso::kExchangeClasses && e == hipSuccess && P.any_exchange; ++c)
         e = dpso::launch_batch_2opt_prepare(c, P.cls[c].members, P.cls[c].max_ns, s);
-    return e;
-}
-
-// The launches of one generation of a batch; the move and exchange classes
-// fan out when `f` is given. Every kernel reads the generation counter and
-// the stop flags from the states, so the same launches serve every
-// generation.
-hipError_t enqueue_batch_generation(const BatchPlan &P, hipStream_t s, Fan *f = nullptr, FanEvents *ev = nullptr)
-{
-    auto move = [&](int c, hipStream_t st) {
-        return dpso::launch_batch_move(move_class_threads(c), P.mv[c].members, P.mv[c].grid, P.mv[c].max_ns, st);
-    };
-    auto exchange = [&](int c, hipStream_t st) {
-        return dpso::launch_batch_2opt(c, P.cls[c].members, P.cls[c].grid, P.cls[c].max_ns, st);
-    };
-    hipError_t e = fan_out(P.mv, kMoveClasses, f, ev, s, move);
-    if (e == hipSuccess && P.any_mutation) e = dpso::launch_batch_mutation(P.items, P.instances, P.total, P.max_ns, s);
-    if (e == hipSuccess) e = dpso::launch_batch_gbest(P.items, P.instances, P.total, P.max_ns, 1, s);
-    if (P.any_exchange) {
-        if (e == hipSuccess) e = fan_out(P.cls, dpso::kExchangeClasses, f, ev, s, exchange);
-        if (e == hipSuccess) e = dpso::launch_batch_gbest(P.items, P.instances, P.total, P.max_ns, 3, s);
-    } else if (e == hipSuccess) {
-        e = dpso::launch_batch_end(P.items, P.instances, P.total, P.max_ns, s);
+    for (int32_t g = 0; g < generations && e == hipSuccess; ++g) {
+        for (int c = 0; c < kMoveClasses && e == hipSuccess; ++c)
+            if (P.mv[c].members.count > 0)
+                e = dpso::launch_batch_move(move_class_threads(c), P.mv[c].members, P.mv[c].grid, P.mv[c].max_ns, s);
+        if (e == hipSuccess && P.any_mutation)
+            e = dpso::launch_batch_mutation(P.items, P.instances, P.total, P.max_ns, s);
+        if (e == hipSuccess) e = dpso::launch_batch_gbest(P.items, P.instances, P.total, P.max_ns, 1, s);
+        if (P.any_exchange) {
+            for (int c = 0; c < dpso::kExchangeClasses && e == hipSuccess; ++c)
+                if (P.cls[c].members.count > 0)
+                    e = dpso::launch_batch_2opt(c, P.cls[c].members, P.cls[c].grid, P.cls[c].max_ns, s);
+            if (e == hipSuccess) e = dpso::launch_batch_gbest(P.items, P.instances, P.total, P.max_ns, 3, s);
+        } else if (e == hipSuccess) {
+            e = dpso::launch_batch_end(P.items, P.instances, P.total, P.max_ns, s);
+        }
     }
     return e;
 }
@@ -1129,35 +1046,24 @@ dpso_status dpso_run_batch(const dpso_batch_item *items, int32_t count, int32_t 
     dpso_status st = plan_batch(items, count, d_work, work_bytes, as_stream(stream), plan);
     if (st) return st;
     hipStream_t s = as_stream(stream);
-    int dev = 0;
-    HIP_TRY(hipGetDevice(&dev), "current device");
-    Fan &fan = g_fans[dev >= 0 && dev < 64 ? dev : 0];
-    std::lock_guard<std::mutex> hold(fan.lock);
-    FanEvents ev;
-    HIP_TRY(fan_setup(fan, ev), "fan-out streams");
-    // on a stream that can be captured, one generation becomes a graph,
-    // instantiated once and launched `generations` times
+    // the whole run as one graph when the stream can be captured
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     const bool graph = s != nullptr && hipStreamIsCapturing(s, &cap) == hipSuccess &&
                        cap == hipStreamCaptureStatusNone && generations > 0;
-    hipError_t e = enqueue_batch_prologue(plan, s);
-    if (graph && e == hipSuccess) {
+    if (graph) HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "begin capture");
+    hipError_t e = enqueue_batch(plan, generations, s);
+    if (graph) {
         hipGraph_t g = nullptr;
+        const hipError_t ec = hipStreamEndCapture(s, &g);
+        if (e == hipSuccess) e = ec;
         hipGraphExec_t x = nullptr;
-        e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
-        if (e == hipSuccess) {
-            e = enqueue_batch_generation(plan, s, &fan, &ev);
-            const hipError_t ec = hipStreamEndCapture(s, &g);
-            if (e == hipSuccess) e = ec;
-        }
         if (e == hipSuccess) e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
-        for (int32_t k = 0; k < generations && e == hipSuccess; ++k) e = hipGraphLaunch(x, s);
+        if (e == hipSuccess) e = hipGraphLaunch(x, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (x) hipGraphExecDestroy(x);
         if (g) hipGraphDestroy(g);
-    } else {
-        for (int32_t k = 0; k < generations && e == hipSuccess; ++k) e = enqueue_batch_generation(plan, s, &fan, &ev);
-        if (e == hipSuccess) e = hipStreamSynchronize(s);
+    } else if (e == hipSuccess) {
+        e = hipStreamSynchronize(s);
     }
     if (e != hipSuccess) return hip_fail(e, "batched run");
     return ok();

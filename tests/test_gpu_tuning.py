@@ -170,8 +170,8 @@ def test_autotune_refuses_a_run_past_max_generations(dp):
 
 
 def test_batch_graph_replays_match_oracle(dp):
-    """dpso_run_batch on a capturable stream replays one captured generation:
-    three calls of three replays each, with the program's own work and a
+    """dpso_run_batch on a capturable stream, called three times (each call
+    captures and launches its own graph), with the program's own work and a
     synchronisation between calls, every call's states against the oracle at
     the same generation."""
     import torch
