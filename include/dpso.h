@@ -349,8 +349,8 @@ dpso_status dpso_init_batch(const dpso_batch_item *items, int32_t count, void *d
  * phase covering all instances' particles (one per move class and one per
  * edge-exchange class, ordered by dpso_batch_order_get), so each kernel
  * boundary synchronises the whole batch and the hardware scheduler balances
- * instances of uneven size. On a non-null stream that is not already
- * capturing, the whole run is captured into one hipGraph and launched once.
+ * instances of uneven size. The launches go to `stream` as they are
+ * enqueued (no graph: capturing thousands of nodes cost more than it saved).
  * Each instance's result is identical to dpso_run on it alone. Synchronises
  * `stream`. */
 dpso_status dpso_run_batch(const dpso_batch_item *items, int32_t count, int32_t generations,

@@ -191,16 +191,15 @@ bool host_velocity_tours(const uint16_t *pairs, int len, int n, uint16_t *from, 
 // prefix tables (per particle, per instance), and for every move class and
 // every edge-exchange class the descriptors of its members with their
 // particle prefix.
-constexpr int kMoveClasses = 15;  // threads per particle 64 / 128 / 256 x 1, 2, 4, 8, 16 positions each
+// Move classes: threads per particle 64 / 128 / 256. A class takes the
+// positions per thread of its largest member (one launch per class: in a
+// small batch several narrow launches one after another cost more than the
+// unrolled positions past a short tour's end).
+constexpr int kMoveClasses = 3;
 
-int move_class(int tpb, int ns)
-{
-    int e = 0;
-    while (e < 4 && ns > (tpb << e)) ++e;
-    return (tpb == 64 ? 0 : tpb == 128 ? 1 : 2) * 5 + e;
-}
+int move_class(int tpb) { return tpb == 64 ? 0 : tpb == 128 ? 1 : 2; }
 
-int move_class_threads(int mc) { return 64 << (mc / 5); }
+int move_class_threads(int mc) { return 64 << mc; }
 
 struct BatchLayout {
     size_t inst, first_items, first_inst, cls_inst[dpso::kExchangeClasses], cls_first[dpso::kExchangeClasses],
@@ -340,7 +339,7 @@ dpso_status plan_batch(const dpso_batch_item *items, int32_t count, void *d_work
         plan.max_ns = std::max(plan.max_ns, L.ns);
         plan.any_mutation |= it.params.mutation_period > 0;
         const dpso::Tune tune = dpso::tuning_for(it.n, total);
-        mv_members[move_class(tune.move_threads, L.ns)].push_back(i);
+        mv_members[move_class(tune.move_threads)].push_back(i);
         if (it.params.ee_trigger != DPSO_EE_OFF) {
             plan.any_exchange = true;
             cls_members[dpso::exchange_class(it.n, it.d_dist, it.params.ee_neighbourhood, tune.exchange_rows)]
@@ -1046,25 +1045,12 @@ dpso_status dpso_run_batch(const dpso_batch_item *items, int32_t count, int32_t 
     dpso_status st = plan_batch(items, count, d_work, work_bytes, as_stream(stream), plan);
     if (st) return st;
     hipStream_t s = as_stream(stream);
-    // the whole run as one graph when the stream can be captured
-    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-    const bool graph = s != nullptr && hipStreamIsCapturing(s, &cap) == hipSuccess &&
-                       cap == hipStreamCaptureStatusNone && generations > 0;
-    if (graph) HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "begin capture");
+    // launched as they are enqueued: the host stays ahead of the GPU (a few
+    // µs a launch against ~0.1-2 ms of kernels a generation), and capturing
+    // the run into a graph first would cost its capture and instantiation
+    // (thousands of nodes) before any work starts
     hipError_t e = enqueue_batch(plan, generations, s);
-    if (graph) {
-        hipGraph_t g = nullptr;
-        const hipError_t ec = hipStreamEndCapture(s, &g);
-        if (e == hipSuccess) e = ec;
-        hipGraphExec_t x = nullptr;
-        if (e == hipSuccess) e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
-        if (e == hipSuccess) e = hipGraphLaunch(x, s);
-        if (e == hipSuccess) e = hipStreamSynchronize(s);
-        if (x) hipGraphExecDestroy(x);
-        if (g) hipGraphDestroy(g);
-    } else if (e == hipSuccess) {
-        e = hipStreamSynchronize(s);
-    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "batched run");
     return ok();
 }

@@ -48,27 +48,33 @@ int tune_bucket_p(int64_t particles)
 }
 
 // Built-in choices, from the autotuner's measurements on MI355X (facades,
-// edge exchange every generation): with more than 2048 particles in flight
-// the GPU is full whatever the width, and one wavefront per particle in the
-// move is fastest up to n = 512 (5-10 % faster generations than 256 threads
-// at n <= 192); a lone small swarm is latency-bound and one wavefront has the
-// cheapest barriers; in between 256 threads fill the GPU best. int32 rows
-// straight into LDS beat 16-bit rows up to n = 512 (n a multiple of 4); above
-// that the 16-bit rows' halved staging wins.
+// edge exchange every generation) and from batched and served runs. With
+// more than 8192 particles in flight the GPU is full whatever the width, and
+// one wavefront per particle in the move is fastest up to n = 512 (5-10 %
+// faster generations than 256 threads at n <= 192), int32 rows straight into
+// LDS beat 16-bit rows up to n = 512 (n a multiple of 4). Below that, a
+// batch's move and exchange classes run one after another and a small batch
+// fills the GPU only with few, large launches, so the defaults keep the
+// classes few: 256 threads per particle (one wavefront for a lone swarm of at
+// most 128 particles, whose barriers it makes cheapest) and int32 rows only
+// for multiples of 4 up to 256, where they take one load chunk either way.
 Tune default_tuning(int n, int64_t particles)
 {
     Tune t;
     const int ns = (n + 63) & ~63;
-    if (particles > 2048)
-        t.move_threads = n <= 512 ? 64 : 256;
-    else if (particles <= 128)
-        t.move_threads = move_threads_ok(64, ns) ? 64 : 256;
-    else
-        t.move_threads = 256;
     const bool aligned = (n & 3) == 0;
+    int i32_up_to = 256;
+    if (particles > 8192) {
+        t.move_threads = n <= 512 ? 64 : 256;
+        i32_up_to = 512;
+    } else if (particles <= 128) {
+        t.move_threads = move_threads_ok(64, ns) ? 64 : 256;
+    } else {
+        t.move_threads = 256;
+    }
     t.exchange_rows = n > 1024 ? DPSO_ROWS_BLOCK
-                      : !packed_rows(n) || (aligned && n <= 512) ? DPSO_ROWS_I32
-                                                                 : DPSO_ROWS_U16;
+                      : !packed_rows(n) || (aligned && n <= i32_up_to) ? DPSO_ROWS_I32
+                                                                       : DPSO_ROWS_U16;
     return t;
 }
 

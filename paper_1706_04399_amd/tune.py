@@ -21,15 +21,14 @@ from . import dpso, scenes
 
 # (n, particles launched together), one per table bucket: the single-instance
 # workloads (facade n = 30 / swarm 64, bridge n = 200 / swarm 1024, facade
-# n = 1000 / swarm 4096), batches of many instances (more than 8192
-# particles) at every n bucket from 32 to 1024, and served batches of a few
-# requests (up to 2048 particles) and single served requests (swarm 512) over
-# n from 50 to 800.
+# n = 1000 / swarm 4096) and batches of many instances (more than 8192
+# particles) at every n bucket from 32 to 1024. Smaller batches (served
+# re-planning: a few requests of 512 particles) keep the built-in defaults:
+# a single instance's fastest configuration can split a small batch into
+# more launches, which run one after another.
 DEFAULT_BUCKETS = [
     (30, 64), (200, 1024), (1000, 4096),
     (24, 16384), (48, 16384), (96, 16384), (192, 16384), (384, 16384), (768, 16384),
-    (48, 2048), (96, 2048), (192, 2048), (384, 2048), (768, 2048),
-    (48, 512), (96, 512), (192, 512), (384, 512), (768, 512),
 ]
 
 

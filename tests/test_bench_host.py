@@ -19,13 +19,13 @@ def test_more_than_one_gpu_is_refused():
 
 
 @pytest.mark.parametrize("n,name", [
-    (1000, "k_2opt_wave<16, true, true>"),    # 16-bit rows (n > 512)
+    (1000, "k_2opt_wave<16, true, true>"),    # 16-bit rows (n > 256 among <= 8192 particles)
     (1024, "k_2opt_wave<16, true, true>"),
     (1021, "k_2opt_wave<16, true, true>"),    # padded 16-bit rows
     (516, "k_2opt_wave<16, true, true>"),
-    (512, "k_2opt_wave<8, true, false>"),     # int32 rows straight into LDS (n <= 512, n % 4 == 0)
-    (260, "k_2opt_wave<8, true, false>"),
-    (256, "k_2opt_wave<4, true, false>"),
+    (512, "k_2opt_wave<8, true, true>"),
+    (260, "k_2opt_wave<8, true, true>"),
+    (256, "k_2opt_wave<4, true, false>"),     # int32 rows straight into LDS (n <= 256, n % 4 == 0)
     (255, "k_2opt_wave<4, true, true>"),      # rows of D off 16 bytes: 16-bit copy
     (64, "k_2opt_wave<1, true, false>"),
     (9, "k_2opt_wave<1, true, true>"),

@@ -63,7 +63,7 @@ def test_workload3_full_run_matches_oracle_digest(dp):
 def test_batch256_matches_oracle_digest(dp):
     """The batched workload (256 instances, n log-uniform in [20, 500], swarm
     256, 500 generations, exchange on stall) in one batched call on a side
-    stream (captured into a graph): every instance's final swarm equals the
+    stream: every instance's final swarm equals the
     oracle's solve of that instance alone."""
     import torch
     want = _load("batch256")

@@ -493,13 +493,13 @@ def _batch_case(gens):
     return members
 
 
-@pytest.mark.parametrize("graph", [False, True], ids=["launches", "graph"])
-def test_batch_matches_oracle(dp, graph):
+@pytest.mark.parametrize("side", [False, True], ids=["null_stream", "side_stream"])
+def test_batch_matches_oracle(dp, side):
     import torch
     gens = 9
     members = _batch_case(gens)
-    stream = torch.cuda.Stream() if graph else None   # the null stream is never captured
-    note(f"batch of {len(members)} instances, graph={graph}")
+    stream = torch.cuda.Stream() if side else None
+    note(f"batch of {len(members)} instances, side stream={side}")
     b = dp.Batch([(_dev(D), p) for D, p in members], stream=stream).init()
     b.run(4)
     b.run(gens - 4)

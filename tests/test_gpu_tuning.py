@@ -169,11 +169,10 @@ def test_autotune_refuses_a_run_past_max_generations(dp):
     assert e.value.status == dp.E_RANGE
 
 
-def test_batch_graph_replays_match_oracle(dp):
-    """dpso_run_batch on a capturable stream, called three times (each call
-    captures and launches its own graph), with the program's own work and a
-    synchronisation between calls, every call's states against the oracle at
-    the same generation."""
+def test_batch_calls_in_a_row_match_oracle(dp):
+    """dpso_run_batch on a side stream, called three times, with the
+    program's own work and a synchronisation between calls, every call's
+    states against the oracle at the same generation."""
     import torch
     members, refs = [], []
     for k, (n, S, kw) in enumerate(BATCH[:9]):
@@ -186,7 +185,7 @@ def test_batch_graph_replays_match_oracle(dp):
     stream = torch.cuda.Stream()
     b = dp.Batch([(_dev(D), p) for D, p in members], stream=stream).init()
     for call in range(3):
-        note(f"batch graph replays, call {call}")
+        note(f"batch calls in a row, call {call}")
         b.run(3)
         stream.synchronize()
         torch.zeros(1 << 20, device="cuda").sum().item()   # other work between the calls
