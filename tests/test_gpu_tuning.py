@@ -193,3 +193,34 @@ def test_batch_calls_in_a_row_match_oracle(dp):
             oracle.run(D, prm, ref, 3)
             bad = mismatches(dp.export_state(st, D.shape[0], prm["swarm_size"], stream), ref)
             assert not bad, f"call {call} instance {k} (n={D.shape[0]}): {bad}"
+
+
+@pytest.mark.parametrize("order", [1, 2, 3], ids=["index", "longest_first", "xcd_groups"])
+def test_batch_orders_match_oracle(dp, order):
+    """Every batch order gives the oracle's swarms: a batch whose classes have
+    8 or more members of equal work (24 instances of n = 50 and eight of
+    n = 97), so XCD groups form and blocks past a group's end do nothing."""
+    import torch
+    gens = 4
+    cases = [(50, 6, dict(ee_trigger=2))] * 24 + [(97, 4, dict(ee_trigger=2))] * 8
+    members, refs = [], []
+    for k, (n, S, kw) in enumerate(cases):
+        sc = scenes.random_points(n, seed=700 + k, n_boxes=2)
+        D = oracle.build_dist(sc)
+        prm = scenes.swarm_params(S, gens, seed=k, instance=k, **kw)
+        ref = oracle.new_state(D, prm)
+        oracle.run(D, prm, ref, gens)
+        members.append((D, prm))
+        refs.append(ref)
+    dp.tuning_reset()
+    dp.batch_order_set(order)
+    try:
+        stream = torch.cuda.Stream()
+        note(f"batch of {len(members)} instances, order {order}")
+        b = dp.Batch([(_dev(D), p) for D, p in members], stream=stream).init()
+        b.run(gens)
+        for k, ((D, prm), st, ref) in enumerate(zip(members, b.states, refs)):
+            bad = mismatches(dp.export_state(st, D.shape[0], prm["swarm_size"], stream), ref)
+            assert not bad, f"order {order} instance {k} (n={D.shape[0]}): {bad}"
+    finally:
+        dp.batch_order_set(0)
