@@ -48,33 +48,31 @@ int tune_bucket_p(int64_t particles)
 }
 
 // Built-in choices, from the autotuner's measurements on MI355X (facades,
-// edge exchange every generation) and from batched and served runs. With
-// more than 8192 particles in flight the GPU is full whatever the width, and
-// one wavefront per particle in the move is fastest up to n = 512 (5-10 %
-// faster generations than 256 threads at n <= 192), int32 rows straight into
-// LDS beat 16-bit rows up to n = 512 (n a multiple of 4). Below that, a
-// batch's move and exchange classes run one after another and a small batch
-// fills the GPU only with few, large launches, so the defaults keep the
-// classes few: 256 threads per particle (one wavefront for a lone swarm of at
-// most 128 particles, whose barriers it makes cheapest) and int32 rows only
-// for multiples of 4 up to 256, where they take one load chunk either way.
+// edge exchange every generation) and from batched and served runs. A lone
+// swarm of at most 1024 particles takes int32 rows straight into LDS for
+// multiples of 4 up to n = 256, where they take one load chunk either way
+// and ran faster than 16-bit rows (n = 200, swarm 1024: 6.4 against 7.1 ms
+// for 64 generations). With more particles in flight — large swarms and
+// batches, whose move and exchange classes run one after another — every
+// n from 8 to 1024 takes 16-bit rows, which keeps one exchange class per
+// column count (the batched workload: 320 solves/s against 290 with int32
+// rows for the multiples of 4). The move runs one wavefront per particle for
+// a lone swarm of at most 128 (the cheapest barriers) and, among more than
+// 8192 particles, for n <= 512 (the GPU is full whatever the width, and
+// narrow blocks waste no lanes); 256 threads otherwise.
 Tune default_tuning(int n, int64_t particles)
 {
     Tune t;
     const int ns = (n + 63) & ~63;
     const bool aligned = (n & 3) == 0;
-    int i32_up_to = 256;
-    if (particles > 8192) {
+    if (particles > 8192)
         t.move_threads = n <= 512 ? 64 : 256;
-        i32_up_to = 512;
-    } else if (particles <= 128) {
+    else if (particles <= 128)
         t.move_threads = move_threads_ok(64, ns) ? 64 : 256;
-    } else {
+    else
         t.move_threads = 256;
-    }
-    t.exchange_rows = n > 1024 ? DPSO_ROWS_BLOCK
-                      : !packed_rows(n) || (aligned && n <= i32_up_to) ? DPSO_ROWS_I32
-                                                                       : DPSO_ROWS_U16;
+    const bool i32 = !packed_rows(n) || (particles <= 1024 && aligned && n <= 256);
+    t.exchange_rows = n > 1024 ? DPSO_ROWS_BLOCK : i32 ? DPSO_ROWS_I32 : DPSO_ROWS_U16;
     return t;
 }
 

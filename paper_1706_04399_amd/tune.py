@@ -21,15 +21,10 @@ from . import dpso, scenes
 
 # (n, particles launched together), one per table bucket: the single-instance
 # workloads (facade n = 30 / swarm 64, bridge n = 200 / swarm 1024, facade
-# n = 1000 / swarm 4096) and batches of many instances (more than 8192
-# particles) at every n bucket from 32 to 1024. Smaller batches (served
-# re-planning: a few requests of 512 particles) keep the built-in defaults:
-# a single instance's fastest configuration can split a small batch into
-# more launches, which run one after another.
-DEFAULT_BUCKETS = [
-    (30, 64), (200, 1024), (1000, 4096),
-    (24, 16384), (48, 16384), (96, 16384), (192, 16384), (384, 16384), (768, 16384),
-]
+# n = 1000 / swarm 4096). Batches keep the built-in defaults: a single
+# instance's fastest configuration can split a batch into more classes,
+# whose launches run one after another.
+DEFAULT_BUCKETS = [(30, 64), (200, 1024), (1000, 4096)]
 
 
 def cache_path(device=None) -> str:

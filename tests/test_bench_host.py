@@ -19,7 +19,7 @@ def test_more_than_one_gpu_is_refused():
 
 
 @pytest.mark.parametrize("n,name", [
-    (1000, "k_2opt_wave<16, true, true>"),    # 16-bit rows (n > 256 among <= 8192 particles)
+    (1000, "k_2opt_wave<16, true, true>"),    # 16-bit rows (n > 256 among <= 1024 particles)
     (1024, "k_2opt_wave<16, true, true>"),
     (1021, "k_2opt_wave<16, true, true>"),    # padded 16-bit rows
     (516, "k_2opt_wave<16, true, true>"),
@@ -37,5 +37,5 @@ def test_exchange_kernel_name_follows_the_default_rows(n, name):
     (the tuning table is read on the host; no GPU)."""
     from paper_1706_04399_amd import dpso
     dpso.tuning_reset()
-    rows = dpso.tuning_get(n, 4096)["exchange_rows"]
+    rows = dpso.tuning_get(n, 1024)["exchange_rows"]
     assert bench.exchange_kernel_name(n, rows) == name

@@ -111,20 +111,21 @@ def test_tuning_table(dp):
     dp.tuning_reset()
     # defaults: one wavefront per particle in the move for a lone swarm of at
     # most 128 and for n <= 512 among more than 8192 particles, else 256
-    # threads; int32 rows for multiples of 4 up to 256 (up to 512 among more
-    # than 8192 particles) and below n = 8, where no 16-bit copy exists,
-    # 16-bit rows for other n up to 1024, one workgroup per particle above
+    # threads; int32 rows for multiples of 4 up to 256 among at most 1024
+    # particles and below n = 8, where no 16-bit copy exists, 16-bit rows for
+    # other n up to 1024, one workgroup per particle above
     assert dp.tuning_get(1000, 4096) == {"move_threads": 256, "exchange_rows": dp.ROWS_U16}
     assert dp.tuning_get(30, 64) == {"move_threads": 64, "exchange_rows": dp.ROWS_U16}
     assert dp.tuning_get(200, 1024) == {"move_threads": 256, "exchange_rows": dp.ROWS_I32}
-    assert dp.tuning_get(200, 65536) == {"move_threads": 64, "exchange_rows": dp.ROWS_I32}
-    assert dp.tuning_get(384, 65536) == {"move_threads": 64, "exchange_rows": dp.ROWS_I32}
-    assert dp.tuning_get(384, 4096) == {"move_threads": 256, "exchange_rows": dp.ROWS_U16}
-    assert dp.tuning_get(385, 65536) == {"move_threads": 64, "exchange_rows": dp.ROWS_U16}
+    assert dp.tuning_get(200, 1025) == {"move_threads": 256, "exchange_rows": dp.ROWS_U16}
+    assert dp.tuning_get(200, 65536) == {"move_threads": 64, "exchange_rows": dp.ROWS_U16}
+    assert dp.tuning_get(384, 65536) == {"move_threads": 64, "exchange_rows": dp.ROWS_U16}
+    assert dp.tuning_get(384, 512) == {"move_threads": 256, "exchange_rows": dp.ROWS_U16}
     assert dp.tuning_get(516, 65536) == {"move_threads": 256, "exchange_rows": dp.ROWS_U16}
     assert dp.tuning_get(2000, 8) == {"move_threads": 256, "exchange_rows": dp.ROWS_BLOCK}
     assert dp.tuning_get(2000, 64)["move_threads"] == 256     # 64 threads serve n <= 1024 only
     assert dp.tuning_get(5, 8)["exchange_rows"] == dp.ROWS_I32
+    assert dp.tuning_get(5, 65536)["exchange_rows"] == dp.ROWS_I32
     try:
         dp.tuning_set(200, 1024, {"move_threads": 128, "exchange_rows": dp.ROWS_U16})
         # the whole bucket: n in (128, 256], 513 .. 1024 particles launched together
