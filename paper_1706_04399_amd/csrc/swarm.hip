@@ -588,6 +588,19 @@ __device__ __forceinline__ void move_body(const Inst &I, int part)
     const uint16_t *xg = st.X + size_t(part) * ns;
     const uint16_t *vref = st.V + size_t(part) * 2 * ns, *vtgt = vref + ns;
     const bool has_v = st.VL[part] != 0;
+    // with few positions per thread, the personal-best and global-best rows
+    // used by the later steps are read now, beside the first loads, so their
+    // memory latency is not paid again in the middle of the step (neither row
+    // changes before this kernel writes P at its end)
+    constexpr bool kPre = EPT <= 4;
+    uint16_t pre_p[kPre ? EPT : 1], pre_g[kPre ? EPT : 1];
+    if constexpr (kPre) {
+        DPSO_EACH(k)
+        {
+            pre_p[e_] = st.P[size_t(part) * ns + k];
+            pre_g[e_] = st.G[k];
+        }
+    }
     DPSO_EACH(k)
     {
         L.z[k] = xg[k];
@@ -622,7 +635,10 @@ __device__ __forceinline__ void move_body(const Inst &I, int part)
         const uint16_t v = xg[k];
         L.x[k] = v;
         L.posx[v] = uint16_t(k);
-        L.to[k] = st.P[size_t(part) * ns + k];
+        if constexpr (kPre)
+            L.to[k] = pre_p[e_];
+        else
+            L.to[k] = st.P[size_t(part) * ns + k];
     }
     __syncthreads();
     // z <- b(z), b the prefix of P - x
@@ -631,7 +647,10 @@ __device__ __forceinline__ void move_body(const Inst &I, int part)
     DPSO_EACH(k)
     {
         L.z[k] = L.cur[L.posx[L.z[k]]];
-        L.to[k] = st.G[k];
+        if constexpr (kPre)
+            L.to[k] = pre_g[e_];
+        else
+            L.to[k] = st.G[k];
     }
     __syncthreads();
     // z <- c(z), c the prefix of G - x
@@ -972,10 +991,14 @@ hipError_t launch_mutation_t(const Target &t, hipStream_t s)
 
 hipError_t launch_gbest_t(const Target &t, int mode, hipStream_t s)
 {
-    if (mode == 0) return launch(k_gbest0, k_gbest0_batch, t, false, 1024, 0, s);
-    if (mode == 1) return launch(k_gbest1, k_gbest1_batch, t, false, 1024, 0, s);
-    if (mode == 2) return launch(k_gbest2, k_gbest2_batch, t, false, 1024, 0, s);
-    return launch(k_gbest2_end, k_gbest2_end_batch, t, false, 1024, 0, s);  // 3: mode 2, then the end
+    // a single instance's reduction takes as many threads as particles (one
+    // wavefront for a swarm of 64: no idle waves, no workgroup barrier work);
+    // a batch's blocks serve swarms of every size
+    const int threads = t.one ? std::min(1024, std::max(64, (t.one->st.S + 63) & ~63)) : 1024;
+    if (mode == 0) return launch(k_gbest0, k_gbest0_batch, t, false, threads, 0, s);
+    if (mode == 1) return launch(k_gbest1, k_gbest1_batch, t, false, threads, 0, s);
+    if (mode == 2) return launch(k_gbest2, k_gbest2_batch, t, false, threads, 0, s);
+    return launch(k_gbest2_end, k_gbest2_end_batch, t, false, threads, 0, s);  // 3: mode 2, then the end
 }
 
 hipError_t launch_end_t(const Target &t, hipStream_t s)
