@@ -533,6 +533,9 @@ def main():
                     help="time the voxel-grid planner (this many builds per case) instead")
     ap.add_argument("--no-tune", action="store_true",
                     help="use the library's built-in launch configuration instead of the autotuner's picks")
+    ap.add_argument("--batch-merge", type=int, default=-1,
+                    help="batches of at most this many particles launch their 16-bit row exchange "
+                         "classes as one (0: never; default: the library's)")
     ap.add_argument("--batch-order", type=int, default=0,
                     help="order of the batched launches: 0 default, 1 index, 2 longest first, 3 XCD groups")
     args = ap.parse_args()
@@ -547,6 +550,8 @@ def main():
         tuning = setup_tuning(not args.no_tune)
         dpso.batch_order_set(args.batch_order)
         tuning["batch_order"] = dpso.batch_order_get()
+        dpso.batch_merge_set(args.batch_merge)
+        tuning["batch_merge_particles"] = dpso.batch_merge_get()
     if args.batch:
         print(json.dumps(bench_batch(args.batch, args.batch_generations,
                                      0.0 if args.no_cpu else args.cpu_seconds,

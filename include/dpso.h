@@ -347,7 +347,8 @@ dpso_status dpso_init_batch(const dpso_batch_item *items, int32_t count, void *d
 
 /* dpso_run for many independent swarms: every generation is one launch per
  * phase covering all instances' particles (one per move class and one per
- * edge-exchange class, ordered by dpso_batch_order_get), so each kernel
+ * edge-exchange class, the 16-bit row classes of a small batch merged into
+ * one (dpso_batch_merge_set), ordered by dpso_batch_order_get), so each kernel
  * boundary synchronises the whole batch and the hardware scheduler balances
  * instances of uneven size. The launches go to `stream` as they are
  * enqueued (no graph: capturing thousands of nodes cost more than it saved).
@@ -440,6 +441,20 @@ dpso_status dpso_batch_order_set(int32_t order);
 /* The batch order in use on the current device (never DPSO_ORDER_DEFAULT).
  * Host only. */
 int32_t dpso_batch_order_get(void);
+
+/* Merged edge-exchange launches in batched runs, per device. Instances whose
+ * exchange stages 16-bit rows (one wavefront per particle) fall into classes
+ * by the columns each lane holds (n up to 64, 128, 256, 512, 1024). A batch of
+ * at most `max_particles` particles runs all of them in one launch, each
+ * workgroup running its own instance's class code, so instances of different
+ * n run side by side; a larger batch launches the classes one after another.
+ * Results are the same either way. 0 never merges; a negative value restores
+ * the default. Host only. */
+#define DPSO_MERGE_DEFAULT_PARTICLES 8192
+dpso_status dpso_batch_merge_set(int64_t max_particles);
+
+/* The merge limit in use on the current device. Host only. */
+int64_t dpso_batch_merge_get(void);
 
 typedef struct {
     dpso_tuning config;

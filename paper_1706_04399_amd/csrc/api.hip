@@ -291,6 +291,7 @@ struct BatchPlan {
     dpso::Batch items, instances;
     ClassPlan cls[dpso::kExchangeClasses], mv[kMoveClasses];
     int total = 0, max_ns = 0;
+    int mixed = -1;  // the 16-bit row class holding every 16-bit row member, launched mixed
     bool any_mutation = false, any_exchange = false;
 };
 
@@ -344,6 +345,24 @@ dpso_status plan_batch(const dpso_batch_item *items, int32_t count, void *d_work
             plan.any_exchange = true;
             cls_members[dpso::exchange_class(it.n, it.d_dist, it.params.ee_neighbourhood, tune.exchange_rows)]
                 .push_back(i);
+        }
+    }
+    // a batch small enough merges its 16-bit row classes into the largest
+    // (one launch, each instance with its own class's code)
+    if (total <= dpso::batch_merge()) {
+        int top = -1, classes = 0;
+        for (int c = 0; c < dpso::kExchangeClasses; ++c)
+            if (dpso::exchange_class_half(c) && !cls_members[c].empty()) {
+                top = c;
+                ++classes;
+            }
+        if (classes > 1) {
+            for (int c = 0; c < top; ++c)
+                if (dpso::exchange_class_half(c)) {
+                    cls_members[top].insert(cls_members[top].end(), cls_members[c].begin(), cls_members[c].end());
+                    cls_members[c].clear();
+                }
+            plan.mixed = top;
         }
     }
     first_items[count] = int32_t(total);
@@ -404,8 +423,9 @@ dpso_status plan_batch(const dpso_batch_item *items, int32_t count, void *d_work
 
 // All launches of `generations` generations of a batch: per generation, one
 // move launch per move class, the mutation, the first global best, one
-// exchange launch per exchange class and the second global best (with the
-// end of the generation), one after another on `s`.
+// exchange launch per exchange class (the merged 16-bit row classes as one)
+// and the second global best (with the end of the generation), one after
+// another on `s`.
 hipError_t enqueue_batch(const BatchPlan &P, int32_t generations, hipStream_t s)
 {
     hipError_t e = dpso::launch_batch_check(P.items, P.instances, P.total, P.max_ns, s);
@@ -421,7 +441,9 @@ hipError_t enqueue_batch(const BatchPlan &P, int32_t generations, hipStream_t s)
         if (P.any_exchange) {
             for (int c = 0; c < dpso::kExchangeClasses && e == hipSuccess; ++c)
                 if (P.cls[c].members.count > 0)
-                    e = dpso::launch_batch_2opt(c, P.cls[c].members, P.cls[c].grid, P.cls[c].max_ns, s);
+                    e = c == P.mixed
+                            ? dpso::launch_batch_2opt_mixed(c, P.cls[c].members, P.cls[c].grid, P.cls[c].max_ns, s)
+                            : dpso::launch_batch_2opt(c, P.cls[c].members, P.cls[c].grid, P.cls[c].max_ns, s);
             if (e == hipSuccess) e = dpso::launch_batch_gbest(P.items, P.instances, P.total, P.max_ns, 3, s);
         } else if (e == hipSuccess) {
             e = dpso::launch_batch_end(P.items, P.instances, P.total, P.max_ns, s);

@@ -38,6 +38,11 @@ hipError_t launch_batch_end(const Batch &items, const Batch &instances, int tota
 constexpr int kExchangeClasses = 17;
 hipError_t launch_2opt(const Inst &I, int cls, hipStream_t s);
 hipError_t launch_batch_2opt(int cls, const Batch &items, int total, int max_ns, hipStream_t s);
+// Classes that stage 16-bit rows (one wavefront per particle) can share a
+// launch: launch_batch_2opt_mixed runs `items`, instances of that class or of
+// smaller 16-bit row classes, in one launch, each with its own class's body.
+bool exchange_class_half(int cls);
+hipError_t launch_batch_2opt_mixed(int cls, const Batch &items, int total, int max_ns, hipStream_t s);
 // Per-run set-up of the exchange: classes that stage 16-bit rows refresh the
 // state's packed copy of D (after the run's first launch, which clears the
 // header's maximum). `members` is a class's instance table; max_n bounds n.

@@ -16,9 +16,12 @@ constexpr int kMaxDevices = 64;
 struct Table {
     Tune entry[kTuneNBuckets][kTunePBuckets];  // {0, 0}: empty
     int order;                                 // DPSO_ORDER_*, 0: default
+    bool merge_set;                            // false: the default merge limit
+    int64_t merge;                             // batches of at most this many particles merge
 };
 
 constexpr int kDefaultOrder = DPSO_ORDER_LPT;
+constexpr int64_t kDefaultMerge = DPSO_MERGE_DEFAULT_PARTICLES;
 
 std::mutex g_table_mutex;
 Table g_tables[kMaxDevices];
@@ -99,6 +102,13 @@ int batch_order()
     return o == DPSO_ORDER_DEFAULT ? kDefaultOrder : o;
 }
 
+int64_t batch_merge()
+{
+    std::lock_guard<std::mutex> lock(g_table_mutex);
+    const Table &t = g_tables[current_device()];
+    return t.merge_set ? t.merge : kDefaultMerge;
+}
+
 Tune tuning_for(int n, int64_t particles)
 {
     Tune t{0, 0};
@@ -169,5 +179,16 @@ dpso_status dpso_batch_order_set(int32_t order)
 }
 
 int32_t dpso_batch_order_get(void) { return dpso::batch_order(); }
+
+dpso_status dpso_batch_merge_set(int64_t max_particles)
+{
+    std::lock_guard<std::mutex> lock(dpso::g_table_mutex);
+    dpso::Table &t = dpso::g_tables[dpso::current_device()];
+    t.merge_set = max_particles >= 0;
+    t.merge = max_particles;
+    return ok();
+}
+
+int64_t dpso_batch_merge_get(void) { return dpso::batch_merge(); }
 
 }  // extern "C"

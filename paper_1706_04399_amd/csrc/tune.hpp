@@ -34,6 +34,10 @@ Tune tuning_for(int n, int64_t particles);
 // The batch order of the current device (DPSO_ORDER_INDEX, _LPT or _XCD).
 int batch_order();
 
+// Batches of at most this many particles run their 16-bit row exchange
+// classes in one launch (current device).
+int64_t batch_merge();
+
 // The exchange class of an instance under a configuration (see
 // twoopt.hip); D's alignment decides between the int32 kernels.
 int exchange_class(int n, const int32_t *D, int neighbourhood, int rows);

@@ -711,6 +711,32 @@ __global__ __launch_bounds__(64, DPSO_2OPT_WAVES) void k_2opt_wave_batch(Batch B
     twoopt_wave_body<MB, VEC4, HALF>(I, p);
 }
 
+// Instances of several 16-bit row classes (up to MBMAX columns per lane) in
+// one launch: each workgroup runs the body of its own instance's class, the
+// code it runs in that class's launch, so instances of different n run side
+// by side instead of one class after another. The dynamic LDS is sized for
+// MBMAX; a smaller body uses the front of it.
+template <int MBMAX>
+__global__ __launch_bounds__(64, DPSO_2OPT_WAVES) void k_2opt_wave_mixed(Batch B)
+{
+    int p;
+    const int b = batch_item(B, int(blockIdx.x));
+    if (b < 0) return;
+    const Inst &I = batch_pick(B, b, p);
+    const int n = I.st.n;  // uniform: the class bounds of exchange_class
+    if constexpr (MBMAX >= 16) {
+        if (n > 512) return twoopt_wave_body<16, true, true>(I, p);
+    }
+    if constexpr (MBMAX >= 8) {
+        if (n > 256) return twoopt_wave_body<8, true, true>(I, p);
+    }
+    if constexpr (MBMAX >= 4) {
+        if (n > 128) return twoopt_wave_body<4, true, true>(I, p);
+    }
+    if (n > 64) return twoopt_wave_body<2, true, true>(I, p);
+    twoopt_wave_body<1, true, true>(I, p);
+}
+
 // Packed rows of one instance: the largest entry of D (into the header,
 // cleared by the run's first launch), then H = D >> shift. Grid-stride over
 // the n^2 entries; blockIdx.y picks the instance of a batch.
@@ -787,6 +813,16 @@ hipError_t launch_wave(const Inst *one, const Batch &B, int grid, int max_ns, hi
         k_2opt_wave<MB, VEC4, HALF><<<grid, 64, lds, s>>>(*one);
     else
         k_2opt_wave_batch<MB, VEC4, HALF><<<grid, 64, lds, s>>>(B);
+    return hipGetLastError();
+}
+
+template <int MBMAX>
+hipError_t launch_mixed(const Batch &B, int grid, int max_ns, hipStream_t s)
+{
+    const size_t lds = size_t(WaveCfg<MBMAX, true>::GUARD + 2 * WaveCfg<MBMAX, true>::STRIDE) * 4 + size_t(max_ns) * 2;
+    hipError_t e = allow_lds(k_2opt_wave_mixed<MBMAX>, lds);
+    if (e != hipSuccess || grid <= 0) return e;
+    k_2opt_wave_mixed<MBMAX><<<grid, 64, lds, s>>>(B);
     return hipGetLastError();
 }
 
@@ -871,6 +907,20 @@ hipError_t launch_2opt(const Inst &I, int cls, hipStream_t s)
 hipError_t launch_batch_2opt(int cls, const Batch &items, int total, int max_ns, hipStream_t s)
 {
     return launch_class(cls, nullptr, items, total, max_ns, s);
+}
+
+bool exchange_class_half(int cls) { return half_class(cls); }
+
+hipError_t launch_batch_2opt_mixed(int cls, const Batch &items, int total, int max_ns, hipStream_t s)
+{
+    if (!half_class(cls)) return hipErrorInvalidValue;
+    switch (cls - kFirstHalfClass) {
+    case 0: return launch_class(cls, nullptr, items, total, max_ns, s);  // one column per lane: one body
+    case 1: return launch_mixed<2>(items, total, max_ns, s);
+    case 2: return launch_mixed<4>(items, total, max_ns, s);
+    case 3: return launch_mixed<8>(items, total, max_ns, s);
+    default: return launch_mixed<16>(items, total, max_ns, s);
+    }
 }
 
 }  // namespace dpso

@@ -24,6 +24,7 @@ EE_OFF, EE_ON_STALL, EE_ALWAYS = 0, 1, 2
 NB_TWO_OPT, NB_NODE_SWAP = 0, 1
 ROWS_AUTO, ROWS_U16, ROWS_I32, ROWS_BLOCK = 0, 1, 2, 3
 ORDER_DEFAULT, ORDER_INDEX, ORDER_LPT, ORDER_XCD = 0, 1, 2, 3
+MERGE_DEFAULT_PARTICLES = 8192
 
 
 class DpsoError(RuntimeError):
@@ -132,6 +133,8 @@ EXPORTS = {
     "dpso_tuning_reset": (C.c_int32, []),
     "dpso_batch_order_set": (C.c_int32, [C.c_int32]),
     "dpso_batch_order_get": (C.c_int32, []),
+    "dpso_batch_merge_set": (C.c_int32, [C.c_int64]),
+    "dpso_batch_merge_get": (C.c_int64, []),
     "dpso_autotune": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_size_t, C.c_int32,
                                   C.c_void_p, C.c_size_t, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
                                   C.c_void_p]),
@@ -423,6 +426,16 @@ def batch_order_set(order: int):
 
 def batch_order_get() -> int:
     return int(lib().dpso_batch_order_get())
+
+
+def batch_merge_set(max_particles: int):
+    """Batches of at most this many particles run their 16-bit row exchange
+    classes in one launch (0: never, negative: the library default)."""
+    _check(lib().dpso_batch_merge_set(int(max_particles)))
+
+
+def batch_merge_get() -> int:
+    return int(lib().dpso_batch_merge_get())
 
 
 def autotune(D: torch.Tensor, params, state: torch.Tensor, generations: int, stream=None) -> dict:

@@ -237,6 +237,7 @@ inline uint32_t emu_add_sat(uint32_t a, uint32_t b)
 
 typedef int hipError_t;
 constexpr hipError_t hipSuccess = 0;
+constexpr hipError_t hipErrorInvalidValue = 1;
 constexpr hipError_t hipErrorInvalidConfiguration = 9;
 typedef void *hipStream_t;
 typedef void *hipEvent_t;

@@ -361,6 +361,42 @@ def case_orders(emu: Emu) -> bool:
     return ok
 
 
+def case_merge(emu: Emu) -> bool:
+    """One batch with instances of every 16-bit row class (n = 9 ... 601, n not
+    a multiple of 4 so small n take 16-bit rows too) beside int32, node-swap
+    and row-per-workgroup ones, with the 16-bit row classes merged into one
+    launch and launched one after another."""
+    ok = True
+    gens = 3
+    L = emu.L
+    L.dpso_batch_merge_set.argtypes = [C.c_int64]
+    L.dpso_batch_merge_get.restype = C.c_int64
+    cases = [(9, 3, dict(ee_trigger=2)), (50, 4, dict(ee_trigger=2)), (70, 3, dict(ee_trigger=2)),
+             (130, 2, dict(ee_trigger=2)), (301, 2, dict(ee_trigger=2)), (601, 2, dict(ee_trigger=2)),
+             (62, 3, dict(ee_trigger=2)), (5, 3, dict(ee_trigger=2)), (40, 2, dict(ee_trigger=2)),
+             (33, 2, dict(ee_trigger=2, ee_neighbourhood=1)), (1030, 1, dict(ee_trigger=2))]
+    refs = None
+    for limit in (1 << 40, 0):
+        L.dpso_batch_merge_set(limit)
+        ok &= L.dpso_batch_merge_get() == limit
+        members, rr = _batch_members(emu, cases, gens)
+        if refs is None:
+            refs = []
+            for (D, n, prm, st), (Dref, _) in zip(members, rr):
+                ref = oracle.new_state(Dref, prm)
+                oracle.run(Dref, prm, ref, gens)
+                refs.append(ref)
+        emu.init_batch(members)
+        emu.run_batch(members, gens)
+        for k, ((D, n, prm, st), ref) in enumerate(zip(members, refs)):
+            ok &= compare(f"merge limit {limit} instance {k} n={n}", emu.export(st, n, prm["swarm_size"]), ref)
+            emu.free(D)
+            emu.free(st[0])
+    L.dpso_batch_merge_set(-1)
+    ok &= L.dpso_batch_merge_get() == 8192
+    return ok
+
+
 def case_plain(emu: Emu, count: int) -> bool:
     """The batched workload's instances (n log-uniform in [20, 500]) solved
     one after another on the single-instance path, swarm 8, 6 generations."""
@@ -452,6 +488,8 @@ def main(argv):
         ok = case_tuned(emu, len(argv) > 1 and argv[1] == "full")
     elif case == "orders":
         ok = case_orders(emu)
+    elif case == "merge":
+        ok = case_merge(emu)
     elif case == "autotune":
         ok = case_autotune(emu)
     elif case == "plain":

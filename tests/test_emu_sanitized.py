@@ -71,3 +71,9 @@ def test_autotune_under_sanitizers(emu_lib):
 def test_batch_orders_under_sanitizers(emu_lib):
     """Index order, longest-first order and XCD groups give the oracle's swarms."""
     _run("orders")
+
+
+def test_merged_exchange_classes_under_sanitizers(emu_lib):
+    """16-bit row classes merged into one launch and launched one after
+    another give the oracle's swarms, beside the classes that never merge."""
+    _run("merge")

@@ -224,3 +224,39 @@ def test_batch_orders_match_oracle(dp, order):
             assert not bad, f"order {order} instance {k} (n={D.shape[0]}): {bad}"
     finally:
         dp.batch_order_set(0)
+
+
+@pytest.mark.parametrize("limit", [0, 1 << 40], ids=["classes_in_turn", "merged"])
+def test_batch_merged_exchange_matches_oracle(dp, limit):
+    """The 16-bit row classes of a batch (n = 9 ... 1001, n not a multiple of
+    4 so that small n stage 16-bit rows too) launched one after another and
+    merged into one launch, beside classes that never merge (int32 rows,
+    node-swap, row-per-workgroup): every swarm equals the oracle's."""
+    import torch
+    gens = 4
+    ee = dict(ee_trigger=2)
+    cases = [(9, 8, ee), (50, 16, ee), (62, 8, ee), (70, 12, ee), (130, 8, ee), (255, 6, ee),
+             (301, 6, ee), (509, 4, ee), (601, 4, ee), (1001, 3, ee), (40, 8, ee), (5, 8, ee),
+             (33, 4, dict(ee_trigger=2, ee_neighbourhood=1)), (1030, 2, ee), (257, 4, {})]
+    members, refs = [], []
+    for k, (n, S, kw) in enumerate(cases):
+        sc = scenes.random_points(n, seed=900 + k, n_boxes=2 if n > 3 else 0)
+        D = oracle.build_dist(sc)
+        prm = scenes.swarm_params(S, gens, seed=k, instance=k, **kw)
+        ref = oracle.new_state(D, prm)
+        oracle.run(D, prm, ref, gens)
+        members.append((D, prm))
+        refs.append(ref)
+    dp.tuning_reset()
+    dp.batch_merge_set(limit)
+    try:
+        stream = torch.cuda.Stream()
+        note(f"batch of {len(members)} instances, merge limit {limit}")
+        b = dp.Batch([(_dev(D), p) for D, p in members], stream=stream).init()
+        b.run(gens)
+        for k, ((D, prm), st, ref) in enumerate(zip(members, b.states, refs)):
+            bad = mismatches(dp.export_state(st, D.shape[0], prm["swarm_size"], stream), ref)
+            assert not bad, f"merge limit {limit} instance {k} (n={D.shape[0]}): {bad}"
+    finally:
+        dp.batch_merge_set(-1)
+

@@ -174,10 +174,19 @@ def test_tuning_table(dp):
             with pytest.raises(dp.DpsoError) as e:
                 dp.batch_order_set(bad)
             assert e.value.status == dp.E_INVAL
+        # the merge limit of the batched exchange classes
+        assert dp.batch_merge_get() == dp.MERGE_DEFAULT_PARTICLES
+        for m in (0, 1, 1 << 40):
+            dp.batch_merge_set(m)
+            assert dp.batch_merge_get() == m
+        dp.batch_merge_set(-5)
+        assert dp.batch_merge_get() == dp.MERGE_DEFAULT_PARTICLES
+        dp.batch_merge_set(3)
     finally:
         dp.tuning_reset()
     assert dp.tuning_get(1024, 64)["move_threads"] == 64
     assert dp.batch_order_get() == dp.ORDER_LPT
+    assert dp.batch_merge_get() == dp.MERGE_DEFAULT_PARTICLES
 
 
 def test_autotune_validation(dp):
