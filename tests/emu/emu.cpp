@@ -249,11 +249,20 @@ void run_grid(std::function<void()> body, dim3 grid, dim3 block, size_t dyn_lds)
 
 }  // namespace emu
 
-void emu_waitcnt_vmem_zero()
+void emu_waitcnt_vmem(int keep)
 {
     auto &q = ::emu::g_blk->dma[::emu::g_lane->index / 64];
-    for (const auto &d : q) memcpy(d.dst, d.src, d.bytes);
-    q.clear();
+    const int me = ::emu::g_lane->index;
+    const uint64_t issued = ::emu::g_lane->dma_issued;
+    size_t out = 0;
+    for (size_t k = 0; k < q.size(); ++k) {
+        const auto &d = q[k];
+        if (d.lane == me && d.seq + uint64_t(keep) < issued)
+            memcpy(d.dst, d.src, d.bytes);
+        else
+            q[out++] = d;
+    }
+    q.resize(out);
 }
 
 void emu_amdgcn_global_load_lds(const void *src, void *lds, int size, int offset, int aux)
@@ -266,7 +275,9 @@ void emu_amdgcn_global_load_lds(const void *src, void *lds, int size, int offset
                     B->lds_bytes);
     volatile unsigned char probe = *static_cast<const volatile unsigned char *>(src);  // checked read
     (void)probe;
-    B->dma[::emu::g_lane->index / 64].push_back({dst, static_cast<const unsigned char *>(src), size_t(size)});
+    ::emu::Lane *L = ::emu::g_lane;
+    B->dma[L->index / 64].push_back({dst, static_cast<const unsigned char *>(src), size_t(size), L->index,
+                                     L->dma_issued++});
 }
 
 namespace {

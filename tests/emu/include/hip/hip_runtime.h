@@ -67,12 +67,15 @@ struct Lane {
     void *sp = nullptr;
     void *fake = nullptr;  // AddressSanitizer's fake stack of this fiber
     unsigned char *stack = nullptr;
+    uint64_t dma_issued = 0;  // direct LDS loads this thread has issued
 };
 
 struct Dma {
     unsigned char *dst;
     const unsigned char *src;
     size_t bytes;
+    int lane;      // issuing thread
+    uint64_t seq;  // its issue number within that thread
 };
 
 struct BlockCtx {
@@ -186,13 +189,15 @@ inline void emu_wave_sync() { ::emu::wave_op(::emu::kSync, 0); }
 inline void emu_amdgcn_wave_barrier() { emu_wave_sync(); }
 #define emu_amdgcn_fence(...) emu_wave_sync()
 
-// s_waitcnt: vmcnt in bits 3:0 and 15:14; at vmcnt 0 the queued direct LDS
-// loads of this wavefront land.
-void emu_waitcnt_vmem_zero();
+// s_waitcnt: vmcnt in bits 3:0 and 15:14 (63: no wait). At vmcnt(N) every
+// direct LDS load of the calling thread but its last N lands (loads complete
+// in issue order; only these loads are counted, so a wait lands no more than
+// the hardware's would).
+void emu_waitcnt_vmem(int keep);
 inline void emu_amdgcn_s_waitcnt(int imm)
 {
     const int vm = (imm & 0xF) | ((imm >> 14) & 3) << 4;
-    if (vm == 0) emu_waitcnt_vmem_zero();
+    if (vm < 63) emu_waitcnt_vmem(vm);
     emu_wave_sync();
 }
 // global_load_lds: lane l's `size` bytes from `src` land at lds + offset + size * l.
