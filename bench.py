@@ -31,6 +31,8 @@ HBM_PEAK_GBS = 8000.0
 
 VALU_LANE_OPS_PER_S = 256 * 4 * 16 * 2.4e9
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_facade1000.md")
+# continuous batching of the served runs: rounds of at most this many generations
+SERVE_CHUNK = 32
 KERNEL_SRC = os.path.join(ROOT, "paper_1706_04399_amd", "csrc", "twoopt.hip")
 
 
@@ -282,7 +284,7 @@ def bench_batch(count: int, generations: int, cpu_seconds: float = 0.0, plain_le
 
 
 def bench_serve(count: int, rate: float, warmup: int, budget_mb: int, one_at_a_time: bool = False,
-                sites: int = 100, plain: bool = False):
+                sites: int = 100, plain: bool = False, chunk: int = 0):
     """Served re-planning: Poisson arrivals at `rate`/s over `sites` sites (n
     log-uniform in [50, 800], facades and bridges), swarm 512, 300 generations
     per request, one in five re-plans after a moved obstacle; sites keep their
@@ -291,7 +293,9 @@ def bench_serve(count: int, rate: float, warmup: int, budget_mb: int, one_at_a_t
     and run as batches. With `one_at_a_time`, every admitted batch holds one
     request; with `plain` as well, each request runs on the plain
     single-instance path (dpso_init_nn, dpso_run) instead of a batch of one
-    (the baseline)."""
+    (the baseline). With `chunk` > 0 the batched server batches continuously:
+    running swarms advance in rounds of at most `chunk` generations and
+    waiting requests join between rounds."""
     import torch
     from paper_1706_04399_amd import serve
 
@@ -303,8 +307,9 @@ def bench_serve(count: int, rate: float, warmup: int, budget_mb: int, one_at_a_t
     torch.cuda.synchronize()
     ex = serve.GpuExecutor(budget, single=plain)
     sched = serve.Scheduler(budget, ex.footprint, max_batch=1 if one_at_a_time or plain else 1024)
+    chunk = 0 if one_at_a_time or plain else chunk
     t0 = time.perf_counter()
-    recs = serve.serve(reqs, ex, sched)
+    recs = serve.serve(reqs, ex, sched, chunk=chunk)
     wall = time.perf_counter() - t0
     s = serve.summary(recs, warmup=warmup, scheduler=sched)
     return {
@@ -323,8 +328,9 @@ def bench_serve(count: int, rate: float, warmup: int, budget_mb: int, one_at_a_t
                                f"after a moved obstacle, {count} requests (first {warmup} not "
                                f"counted), budget {budget_mb} MiB",
                    "server": "one request at a time on the single-instance path" if plain else
-                             "one request per batch" if one_at_a_time else "batched, FCFS admission, "
-                             "resident sites"},
+                             "one request per batch" if one_at_a_time else
+                             f"continuous batching (rounds of at most {chunk} generations), FCFS "
+                             "admission, resident sites" if chunk else "batched, FCFS admission, resident sites"},
     }
 
 
@@ -519,6 +525,9 @@ def main():
                     help="serve this many re-planning requests instead")
     ap.add_argument("--rate", type=float, default=50.0)
     ap.add_argument("--serve-warmup", type=int, default=200)
+    ap.add_argument("--serve-chunk", type=int, default=SERVE_CHUNK,
+                    help="continuous batching: rounds of at most this many generations "
+                         "(0: whole batches)")
     ap.add_argument("--budget-mb", type=int, default=2048)
     ap.add_argument("--plain", action="store_true",
                     help="with --serve: one request at a time on the single-instance path")
@@ -565,7 +574,8 @@ def main():
         return
     if args.serve:
         print(json.dumps(bench_serve(args.serve, args.rate, min(args.serve_warmup, args.serve // 4),
-                                     args.budget_mb, args.one_per_batch, plain=args.plain)), flush=True)
+                                     args.budget_mb, args.one_per_batch, plain=args.plain,
+                                     chunk=args.serve_chunk)), flush=True)
         return
 
     import torch
@@ -707,7 +717,8 @@ def main():
     if not args.no_extras:
         line["workloads"] = {"facade30": small_workload(1, 5), "bridge200": small_workload(2, 5)}
         line["batched"] = compact_batch(bench_batch(256, 500))
-        line["served"] = compact_serve(bench_serve(args.extra_serve, 50.0, args.extra_serve // 5, 2048))
+        line["served"] = compact_serve(bench_serve(args.extra_serve, 50.0, args.extra_serve // 5, 2048,
+                                                   chunk=args.serve_chunk))
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(line), flush=True)
@@ -752,6 +763,7 @@ def compact_serve(r: dict) -> dict:
     out = {k: r[k] for k in keys}
     out["p99_ms"] = out.pop("value")
     out["workload"] = r["config"]["workload"]
+    out["server"] = r["config"]["server"]
     return out
 
 

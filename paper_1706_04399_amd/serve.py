@@ -20,7 +20,14 @@ serves a stream of plan requests on one GPU:
   (status ``E_ADMIT``, decided by the library's ``dpso_request_footprint``),
   so the head of the queue always fits; a second request for a site already
   in the batch waits for the next one;
-* the admitted requests run as one batch (`dpso_run_batch`);
+* the admitted requests run as one batch (`dpso_run_batch`); or, with
+  continuous batching (`serve(..., chunk=k)`), the running requests' swarms
+  advance together in rounds of at most k generations, each round one
+  `dpso_run_batch` call that stops at the first request to finish; after a
+  round the finished requests complete and waiting ones join, so a request
+  waits for one round, not for a whole batch, before its swarm runs. A
+  request's result is the same either way: a swarm run in parts equals the
+  swarm run at once;
 * latency is completion time minus arrival time.
 
 The scheduler is independent of the executor, so admission, residency and
@@ -149,8 +156,11 @@ class Scheduler:
     def resident_bytes(self) -> int:
         return sum(self.resident.values())
 
-    def admit(self, queue: collections.deque) -> list:
-        batch, keys, new = [], set(), 0
+    def admit(self, queue: collections.deque, busy=frozenset(), held: int = 0) -> list:
+        """Admits from the head of the queue. `busy`: site keys whose swarm is
+        running (never evicted; a request for one waits); `held`: bytes of
+        running one-off scenes."""
+        batch, keys, new = [], set(busy), held
         while queue and len(batch) < self.max_batch:
             req = queue[0]
             status, need = self.footprint(req)
@@ -158,7 +168,7 @@ class Scheduler:
                 self.rejected.append(queue.popleft())
                 continue
             if req.key and req.key in keys:
-                break                        # its swarm runs in this batch already
+                break                        # its swarm runs in this batch (or is running) already
             cost = 0 if req.key and req.key in self.resident else need
             while self.resident_bytes() + new + cost > self.budget:
                 victim = next((k for k in self.resident if k not in keys), None)
@@ -178,12 +188,17 @@ class Scheduler:
         return batch
 
 
-def serve(requests, executor, scheduler: Scheduler, clock=time.perf_counter, sleep=time.sleep):
+def serve(requests, executor, scheduler: Scheduler, clock=time.perf_counter, sleep=time.sleep,
+          chunk: int = 0):
     """Serves `requests` (sorted by arrival) in real time; returns Records.
 
     executor.solve(batch) returns one dict per request with "cost" and
     optionally "action", "generation" and "tour"; executor.evict(keys), if
-    present, releases the sites the scheduler evicted."""
+    present, releases the sites the scheduler evicted. With chunk > 0 the
+    requests are served by continuous batching (executor.start / step /
+    finish, see `serve_continuous`)."""
+    if chunk > 0:
+        return serve_continuous(requests, executor, scheduler, chunk, clock, sleep)
     pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
     queue = collections.deque()
     records, nbatch = [], 0
@@ -214,6 +229,66 @@ def serve(requests, executor, scheduler: Scheduler, clock=time.perf_counter, sle
                                   OK, res.get("action", ""), int(res.get("generation", -1)),
                                   res.get("tour")))
         nbatch += 1
+    return records
+
+
+def serve_continuous(requests, executor, scheduler: Scheduler, chunk: int, clock=time.perf_counter,
+                     sleep=time.sleep):
+    """Continuous batching. The running requests' swarms advance together,
+    each round min(chunk, fewest generations any running request still
+    needs) generations in one executor.step call; then the requests whose
+    generations are done complete (executor.finish) and the scheduler admits
+    waiting ones (executor.start), which join the next round. A record's
+    `batch` is the round its request joined in.
+
+    executor.start(batch) prepares the requests' swarms and returns one
+    handle each; executor.step(handles, g) runs g generations of all of them;
+    executor.finish(handle) returns the dict executor.solve would."""
+    pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
+    queue = collections.deque()
+    running = []             # [request, handle, generations left, start, round joined]
+    records, rounds = [], 0
+    t0 = clock()
+    while pending or queue or running:
+        now = clock() - t0
+        while pending and pending[0].arrival <= now:
+            queue.append(pending.popleft())
+        if not queue and not running:
+            sleep(max(0.0, pending[0].arrival - now))
+            continue
+        if queue:
+            busy = {r[0].key for r in running if r[0].key}
+            held = sum(scheduler.footprint(r[0])[1] for r in running if not r[0].key)
+            batch = scheduler.admit(queue, busy=busy, held=held)
+            for req in scheduler.rejected:
+                now = clock() - t0
+                records.append(Record(req.rid, req.n, req.arrival, now, now, -1, -1, E_ADMIT, "rejected"))
+            scheduler.rejected.clear()
+            if scheduler.evicted:
+                if hasattr(executor, "evict"):
+                    executor.evict(list(scheduler.evicted))
+                scheduler.evicted.clear()
+            if batch:
+                start = clock() - t0
+                for req, h in zip(batch, executor.start(batch)):
+                    running.append([req, h, req.run_generations, start, rounds])
+        if not running:
+            continue
+        g = min(int(chunk), min(r[2] for r in running))
+        executor.step([r[1] for r in running], g)
+        rounds += 1
+        left = []
+        finished = []
+        for r in running:
+            r[2] -= g
+            (finished if r[2] <= 0 else left).append(r)
+        results = [executor.finish(r[1]) for r in finished]
+        done = clock() - t0
+        for (req, _, _, start, joined), res in zip(finished, results):
+            records.append(Record(req.rid, req.n, req.arrival, start, done, int(res["cost"]), joined,
+                                  OK, res.get("action", ""), int(res.get("generation", -1)),
+                                  res.get("tour")))
+        running = left
     return records
 
 
@@ -280,11 +355,12 @@ class GpuExecutor:
             self.work = self.torch.empty(max(need, 1 << 16), dtype=self.torch.uint8, device="cuda")
         return self.work
 
-    def solve(self, batch):
-        """Actions: "plan" (site not resident: build the matrix, start a swarm),
-        "rebuild" (obstacles changed: rebuild the matrix in place, restart the
-        swarm), "restart" (the swarm's capacity is spent: restart it on the
-        cached matrix), "resume" (run the resident swarm further)."""
+    def _prepare(self, batch):
+        """Each request's site and action: "plan" (site not resident: build the
+        matrix, start a swarm), "rebuild" (obstacles changed: rebuild the matrix
+        in place, restart the swarm), "restart" (the swarm's capacity is spent:
+        restart it on the cached matrix), "resume" (run the resident swarm
+        further). Returns (sites, actions, sites to initialise)."""
         d, torch = self.dpso, self.torch
         sites, actions, cold = [], [], []
         for req in batch:
@@ -311,20 +387,45 @@ class GpuExecutor:
             site.t += G
             sites.append(site)
             actions.append(act)
+        return sites, actions, cold
+
+    def _init(self, cold):
+        if cold:
+            self.dpso.Batch([(s.D, s.params) for s in cold], stream=self.stream,
+                            states=[s.state for s in cold], work=self._work(len(cold))).init()
+
+    def _result(self, site, act):
+        tour, cost, gen, _ = self.dpso.get_best(site.state, self.stream)
+        return {"cost": cost, "action": act, "generation": gen, "tour": tour}
+
+    def start(self, batch):
+        """Continuous batching: prepares the requests' swarms (as solve does)
+        and returns one handle per request."""
+        sites, actions, cold = self._prepare(batch)
+        self._init(cold)
+        return list(zip(sites, actions))
+
+    def step(self, handles, generations):
+        """Runs `generations` generations of the handles' swarms as one batch."""
+        self.dpso.Batch([(s.D, s.params) for s, _ in handles], stream=self.stream,
+                        states=[s.state for s, _ in handles], work=self._work(len(handles))).run(generations)
+
+    def finish(self, handle):
+        return self._result(*handle)
+
+    def solve(self, batch):
+        """Runs the batch's requests to completion (actions: see _prepare)."""
+        d = self.dpso
+        sites, actions, cold = self._prepare(batch)
         if self.single:
             for site, act, req in zip(sites, actions, batch):
                 if act != "resume":
                     d.init_nn(site.D, site.params, site.state, stream=self.stream)
                 d.run(site.D, site.params, site.state, req.run_generations, stream=self.stream)
-        elif cold:
-            d.Batch([(s.D, s.params) for s in cold], stream=self.stream,
-                    states=[s.state for s in cold], work=self._work(len(cold))).init()
+        else:
+            self._init(cold)
         for G in sorted({r.run_generations for r in batch}) if not self.single else ():
             group = [s for s, r in zip(sites, batch) if r.run_generations == G]
             d.Batch([(s.D, s.params) for s in group], stream=self.stream,
                     states=[s.state for s in group], work=self._work(len(group))).run(G)
-        out = []
-        for site, act in zip(sites, actions):
-            tour, cost, gen, _ = d.get_best(site.state, self.stream)
-            out.append({"cost": cost, "action": act, "generation": gen, "tour": tour})
-        return out
+        return [self._result(site, act) for site, act in zip(sites, actions)]

@@ -510,15 +510,17 @@ def test_batch_matches_oracle(dp, side):
         assert not bad, f"instance {k} (n={D.shape[0]}): {bad}"
 
 
-@pytest.mark.parametrize("single", [False, True], ids=["batched", "single_instance"])
-def test_served_replans_match_oracle(dp, single):
+@pytest.mark.parametrize("single,chunk", [(False, 0), (False, 4), (True, 0)],
+                         ids=["batched", "continuous", "single_instance"])
+def test_served_replans_match_oracle(dp, single, chunk):
     """A short re-planning stream through the server (5 sites, obstacle
     changes, swarm capacity of 3 runs, a budget that holds the two largest
     sites, so that sites are evicted): every served plan equals the oracle replaying the same sequence
     of actions per site (a fresh swarm for plan / rebuild / restart on the
     request's scene, the site's previous swarm run further for resume). The
     server runs requests as batches, or one at a time on the single-instance
-    path."""
+    path, or by continuous batching (rounds of at most 4 generations, so
+    swarms run in parts and requests join running ones)."""
     import collections
     from paper_1706_04399_amd import serve
     reqs = serve.replan_requests(40, rate=400.0, seed=9, sites=5, n_lo=20, n_hi=120, swarm=32,
@@ -527,8 +529,8 @@ def test_served_replans_match_oracle(dp, single):
     budget = sizes[-1] + sizes[-2]             # the two largest sites fit together, not all five
     ex = serve.GpuExecutor(budget_bytes=budget, single=single)
     sched = serve.Scheduler(budget, ex.footprint, max_batch=1 if single else 1024)
-    note(f"served re-planning stream of 40 requests against the oracle, single={single}")
-    recs = serve.serve(reqs, ex, sched)
+    note(f"served re-planning stream of 40 requests against the oracle, single={single}, chunk={chunk}")
+    recs = serve.serve(reqs, ex, sched, chunk=chunk)
     assert sorted(r.rid for r in recs) == list(range(40)) and all(r.status == 0 for r in recs)
     acts = collections.Counter(r.action for r in recs)
     assert acts["resume"] and acts["rebuild"] and acts["restart"] and sched.n_evicted > 0, acts

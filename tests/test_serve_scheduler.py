@@ -179,3 +179,75 @@ def test_rejected_requests_are_recorded_not_timed():
     assert all(rid in (0, 2) for b in ex.batches for rid in b)
     s = serve.summary(recs)
     assert s["requests"] == 2 and s["rejected"] == 2
+
+
+class RoundStub:
+    """Continuous-batching executor: a round of g generations takes
+    `per_gen` * g seconds of fake time; records (rids, g) per round and the
+    generations each request ran."""
+
+    def __init__(self, clock, per_gen=0.001):
+        self.clock, self.per = clock, per_gen
+        self.rounds, self.ran = [], collections.Counter()
+
+    def start(self, batch):
+        return [(r.rid, r.n) for r in batch]
+
+    def step(self, handles, g):
+        self.rounds.append(([rid for rid, _ in handles], g))
+        for rid, _ in handles:
+            self.ran[rid] += g
+        self.clock.t += self.per * g
+
+    def finish(self, handle):
+        return {"cost": handle[1]}
+
+
+def _gen_reqs(arrivals, gens, keys=None):
+    sc = scenes.line(list(range(10)))
+    keys = keys or [""] * len(arrivals)
+    return [serve.Request(i, a, sc, scenes.swarm_params(4, 64), key=k, generations=g)
+            for i, (a, g, k) in enumerate(zip(arrivals, gens, keys))]
+
+
+def test_continuous_batching_joins_requests_between_rounds():
+    clock = FakeClock()
+    ex = RoundStub(clock, per_gen=0.001)
+    sched = serve.Scheduler(budget_bytes=10 ** 9, footprint=fp(10 ** 9, 1))
+    recs = serve.serve(_gen_reqs([0.0, 0.0015], [10, 10]), ex, sched, clock=clock, sleep=clock.sleep, chunk=4)
+    # request 1 arrives during the first round and joins the second; rounds
+    # stop at the first request to finish
+    assert ex.rounds == [([0], 4), ([0, 1], 4), ([0, 1], 2), ([1], 4)]
+    assert dict(ex.ran) == {0: 10, 1: 10}
+    by = {r.rid: r for r in recs}
+    assert abs(by[0].start - 0.0) < 1e-12 and abs(by[0].done - 0.010) < 1e-12
+    assert abs(by[1].start - 0.004) < 1e-12 and abs(by[1].done - 0.014) < 1e-12
+    assert (by[0].batch, by[1].batch) == (0, 1)     # the round each joined in
+    assert all(r.cost == 10 for r in recs)
+
+
+def test_continuous_batching_keeps_one_swarm_per_site():
+    clock = FakeClock()
+    ex = RoundStub(clock, per_gen=0.001)
+    sched = serve.Scheduler(budget_bytes=10 ** 9, footprint=fp(10 ** 9, 1))
+    reqs = _gen_reqs([0.0, 0.0, 0.0], [6, 6, 3], keys=["a", "a", "b"])
+    recs = serve.serve(reqs, ex, sched, clock=clock, sleep=clock.sleep, chunk=100)
+    # FCFS: the second "a" waits for the first; "b" is behind it in the queue
+    assert ex.rounds == [([0], 6), ([1, 2], 3), ([1], 3)]
+    by = {r.rid: r for r in recs}
+    assert by[1].start >= by[0].done
+    assert dict(ex.ran) == {0: 6, 1: 6, 2: 3}
+
+
+def test_running_sites_are_never_evicted_and_one_offs_hold_memory():
+    sched = serve.Scheduler(budget_bytes=200, footprint=fp(200, 100))
+    q = collections.deque(_reqs([0.0, 0.0], keys=["a", "b"]))
+    assert [r.rid for r in sched.admit(q)] == [0, 1]
+    q = collections.deque(_reqs([0.0], keys=["c"]))
+    assert [r.rid for r in sched.admit(q, busy={"a"})] == [0]
+    assert sched.evicted == ["b"]                      # "a" is running: "b" goes
+    q = collections.deque(_reqs([0.0], keys=["d"]))
+    assert sched.admit(q, busy={"a", "c"}) == [] and len(q) == 1
+    q = collections.deque(_reqs([0.0]))
+    one_off = serve.Scheduler(budget_bytes=200, footprint=fp(200, 100))
+    assert one_off.admit(q, held=150) == [] and len(q) == 1
