@@ -291,7 +291,7 @@ struct BatchPlan {
     dpso::Batch items, instances;
     ClassPlan cls[dpso::kExchangeClasses], mv[kMoveClasses];
     int total = 0, max_ns = 0;
-    int mixed = -1;  // the 16-bit row class holding every 16-bit row member, launched mixed
+    bool mixed[dpso::kExchangeClasses] = {};  // classes holding a merge group's members, launched mixed
     bool any_mutation = false, any_exchange = false;
 };
 
@@ -347,22 +347,23 @@ dpso_status plan_batch(const dpso_batch_item *items, int32_t count, void *d_work
                 .push_back(i);
         }
     }
-    // a batch small enough merges its 16-bit row classes into the largest
-    // (one launch, each instance with its own class's code)
-    if (total <= dpso::batch_merge()) {
+    // a batch small enough merges the 16-bit row classes of each merge group
+    // (one or two wavefronts per particle) into the group's largest (one
+    // launch, each instance with its own class's code)
+    for (int group = 1; group <= 2 && total <= dpso::batch_merge(); ++group) {
         int top = -1, classes = 0;
         for (int c = 0; c < dpso::kExchangeClasses; ++c)
-            if (dpso::exchange_class_half(c) && !cls_members[c].empty()) {
+            if (dpso::exchange_merge_group(c) == group && !cls_members[c].empty()) {
                 top = c;
                 ++classes;
             }
         if (classes > 1) {
             for (int c = 0; c < top; ++c)
-                if (dpso::exchange_class_half(c)) {
+                if (dpso::exchange_merge_group(c) == group) {
                     cls_members[top].insert(cls_members[top].end(), cls_members[c].begin(), cls_members[c].end());
                     cls_members[c].clear();
                 }
-            plan.mixed = top;
+            plan.mixed[top] = true;
         }
     }
     first_items[count] = int32_t(total);
@@ -441,7 +442,7 @@ hipError_t enqueue_batch(const BatchPlan &P, int32_t generations, hipStream_t s)
         if (P.any_exchange) {
             for (int c = 0; c < dpso::kExchangeClasses && e == hipSuccess; ++c)
                 if (P.cls[c].members.count > 0)
-                    e = c == P.mixed
+                    e = P.mixed[c]
                             ? dpso::launch_batch_2opt_mixed(c, P.cls[c].members, P.cls[c].grid, P.cls[c].max_ns, s)
                             : dpso::launch_batch_2opt(c, P.cls[c].members, P.cls[c].grid, P.cls[c].max_ns, s);
             if (e == hipSuccess) e = dpso::launch_batch_gbest(P.items, P.instances, P.total, P.max_ns, 3, s);
@@ -849,9 +850,10 @@ dpso_status dpso_autotune(const int32_t *d_dist, int32_t n, const dpso_params *p
     const bool exchange = params->ee_trigger != DPSO_EE_OFF && params->ee_neighbourhood == DPSO_NB_TWO_OPT;
     if (exchange) {
         const int tpb = done[best].config.move_threads;
-        for (int rows : {DPSO_ROWS_U16, DPSO_ROWS_I32, DPSO_ROWS_BLOCK}) {
+        for (int rows : {DPSO_ROWS_U16, DPSO_ROWS_I32, DPSO_ROWS_BLOCK, DPSO_ROWS_U16_PAIR}) {
             if (rows == dflt.exchange_rows) continue;
             if (rows == DPSO_ROWS_U16 && !dpso::packed_rows(n)) continue;
+            if (rows == DPSO_ROWS_U16_PAIR && !(dpso::packed_rows(n) && n > 128)) continue;
             if (rows == DPSO_ROWS_I32 && n > 1024) continue;
             // an n off 16 bytes takes 16-bit rows for int32 ones: the same kernel
             if (rows == DPSO_ROWS_I32 && (n & 3) != 0 && dpso::packed_rows(n)) continue;

@@ -35,13 +35,15 @@ hipError_t launch_batch_end(const Batch &items, const Batch &instances, int tota
 // (columns held per lane), on the row form of the configuration and on the
 // alignment of D (exchange_class, tune.hpp); instances of one class share a
 // launch. The last class is the node-swap neighbourhood.
-constexpr int kExchangeClasses = 17;
+constexpr int kExchangeClasses = 20;
 hipError_t launch_2opt(const Inst &I, int cls, hipStream_t s);
 hipError_t launch_batch_2opt(int cls, const Batch &items, int total, int max_ns, hipStream_t s);
-// Classes that stage 16-bit rows (one wavefront per particle) can share a
-// launch: launch_batch_2opt_mixed runs `items`, instances of that class or of
-// smaller 16-bit row classes, in one launch, each with its own class's body.
-bool exchange_class_half(int cls);
+// Classes that stage 16-bit rows can share a launch with the other classes
+// of their merge group (1: one wavefront per particle, 2: two; 0: none):
+// launch_batch_2opt_mixed runs `items`, instances of class `cls` or of
+// smaller classes of its group, in one launch, each with its own class's
+// body.
+int exchange_merge_group(int cls);
 hipError_t launch_batch_2opt_mixed(int cls, const Batch &items, int total, int max_ns, hipStream_t s);
 // Per-run set-up of the exchange: classes that stage 16-bit rows refresh the
 // state's packed copy of D (after the run's first launch, which clears the

@@ -89,8 +89,11 @@ Tune resolve_tuning(Tune t, int n, int64_t particles)
     const int ns = (n + 63) & ~63;
     if (!move_threads_ok(t.move_threads, ns)) t.move_threads = d.move_threads;
     if (t.exchange_rows == DPSO_ROWS_I32 && (n & 3) != 0 && packed_rows(n)) t.exchange_rows = DPSO_ROWS_U16;
+    // two wavefronts per particle split at least 128 rows; smaller n take one
+    if (t.exchange_rows == DPSO_ROWS_U16_PAIR && packed_rows(n) && n <= 128) t.exchange_rows = DPSO_ROWS_U16;
     const bool ok = t.exchange_rows == DPSO_ROWS_BLOCK || (t.exchange_rows == DPSO_ROWS_I32 && n <= 1024) ||
-                    (t.exchange_rows == DPSO_ROWS_U16 && packed_rows(n));
+                    (t.exchange_rows == DPSO_ROWS_U16 && packed_rows(n)) ||
+                    (t.exchange_rows == DPSO_ROWS_U16_PAIR && packed_rows(n) && n > 128);
     if (!ok) t.exchange_rows = d.exchange_rows;
     return t;
 }
@@ -146,13 +149,14 @@ dpso_status dpso_tuning_set(int32_t n, int32_t particles, const dpso_tuning *t)
     if (t) {
         if (t->move_threads != 0 && t->move_threads != 64 && t->move_threads != 128 && t->move_threads != 256)
             return fail(DPSO_E_INVAL, "move_threads = %d is not 0, 64, 128 or 256", t->move_threads);
-        if (t->exchange_rows < DPSO_ROWS_AUTO || t->exchange_rows > DPSO_ROWS_BLOCK)
+        if (t->exchange_rows < DPSO_ROWS_AUTO || t->exchange_rows > DPSO_ROWS_U16_PAIR)
             return fail(DPSO_E_INVAL, "exchange_rows = %d is not a DPSO_ROWS_* value", t->exchange_rows);
         const int top = dpso::bucket_max_n(bn), ns = (top + 63) & ~63;
         if (t->move_threads != 0 && !dpso::move_threads_ok(t->move_threads, ns))
             return fail(DPSO_E_RANGE, "%d threads per particle cannot serve n = %d (at most 16 positions each)",
                         t->move_threads, top);
-        if ((t->exchange_rows == DPSO_ROWS_U16 || t->exchange_rows == DPSO_ROWS_I32) && n > 1024)
+        if ((t->exchange_rows == DPSO_ROWS_U16 || t->exchange_rows == DPSO_ROWS_I32 ||
+             t->exchange_rows == DPSO_ROWS_U16_PAIR) && n > 1024)
             return fail(DPSO_E_RANGE, "the wavefront exchange serves n up to 1024");
         e.move_threads = t->move_threads;
         e.exchange_rows = t->exchange_rows;

@@ -204,7 +204,7 @@ __device__ inline void dma_row(const int32_t *src, int n, lds_int *dst)
 {
     typedef __attribute__((address_space(1))) const void GV;
     typedef __attribute__((address_space(3))) void LV;
-    const int lane = threadIdx.x, q = (n >> 2) - 1;
+    const int lane = threadIdx.x & 63, q = (n >> 2) - 1;
     compiler_fence();
 #pragma unroll
     for (int k = 0; k < R; ++k)
@@ -248,7 +248,7 @@ __device__ __forceinline__ void place_chunks(const uint16_t *tour, int n, int nc
                                              const unsigned char *&slot_of, int *src_chunk)
 {
     constexpr int RH = (MB + 7) / 8, NHW = 2 * MB, CAP = 8 * RH;
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & 63;  // within the wave (two may share a particle)
     unsigned char *hwpos = scratch;                                             // [64 MB]
     uint32_t *load = reinterpret_cast<uint32_t *>(scratch + 64 * MB);           // [NHW][32]
     uint32_t *mx = load + NHW * 32;                                             // [NHW]
@@ -329,7 +329,7 @@ struct RowPipe {
 
     __device__ inline void load(const int32_t *__restrict__ src, int n)
     {
-        const int lane = threadIdx.x;
+        const int lane = threadIdx.x & 63;
         if constexpr (VEC4) {
             const int4 *s4 = reinterpret_cast<const int4 *>(src);
             const int q = (n >> 2) - 1;
@@ -353,7 +353,7 @@ struct RowPipe {
 
     __device__ inline void store(int32_t *dst, int n) const
     {
-        const int lane = threadIdx.x;
+        const int lane = threadIdx.x & 63;
         if constexpr (VEC4) {
             int4 *d4 = reinterpret_cast<int4 *>(dst);
             const int q = (n >> 2) - 1;
@@ -426,12 +426,12 @@ __device__ inline int lds_half(const int32_t *base, int byte_off)
 template <int MB, bool VEC4, bool HALF, int M0, int BI>
 __device__ __forceinline__ void sweep_row(SweepState<MB, VEC4> &S, const int32_t *__restrict__ D,
                                           const uint16_t *__restrict__ H, int32_t *bufs, lds_int *lbufs,
-                                          const uint16_t *tour, int n, int i)
+                                          const uint16_t *tour, int n, int i, int end)
 {
     constexpr int ST = WaveCfg<MB, VEC4>::STRIDE;
     int32_t *cur = bufs + BI * ST;
     const int32_t *prv = bufs + (1 - BI) * ST;
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & 63;
     int ei;
     if constexpr (HALF) {
         // as below, with ne holding -H[x_c][x_c+1] and off the byte offset
@@ -445,7 +445,8 @@ __device__ __forceinline__ void sweep_row(SweepState<MB, VEC4> &S, const int32_t
         wait_lds();
         compiler_fence();
         const int hs = packed_stride(n);
-        if (i + 4 <= n) dma_half<WaveCfg<MB, VEC4>::RH>(H + size_t(label) * hs, S.src_chunk, lbufs + (1 - BI) * ST);
+        // the next row, if this wave's rows go on (rows end before `end`)
+        if (i + 1 < end) dma_half<WaveCfg<MB, VEC4>::RH>(H + size_t(label) * hs, S.src_chunk, lbufs + (1 - BI) * ST);
     } else if constexpr (kDma && VEC4) {
         // e_i = D[x_i][x_i+1] and the label x_i+2 come from the registers of
         // the lanes owning columns i and i + 1 (in this phase, blocks M0 - 1
@@ -503,35 +504,56 @@ __device__ __forceinline__ void sweep_row(SweepState<MB, VEC4> &S, const int32_t
     }
 }
 
-// Rows [64 M0 - 2, 64 M0 + 62) clipped to [0, n - 2), then the next phase.
+// Rows [64 M0 - 2, 64 M0 + 62) clipped to the wave's rows [begin, end)
+// (begin even; all rows [0, n - 2) for a wave alone), then the next phase.
 template <int MB, bool VEC4, bool HALF, int M0>
 __device__ __forceinline__ void sweep_phase(SweepState<MB, VEC4> &S, const int32_t *__restrict__ D,
                                             const uint16_t *__restrict__ H, int32_t *bufs, lds_int *lbufs,
-                                            const uint16_t *tour, int n)
+                                            const uint16_t *tour, int n, int begin, int end)
 {
-    const int lo = M0 == 0 ? 0 : 64 * M0 - 2;
-    const int hi = min(64 * M0 + 62, n - 2);
+    const int lo = max(M0 == 0 ? 0 : 64 * M0 - 2, begin);
+    const int hi = min(64 * M0 + 62, end);
     for (int i = lo; i < hi; i += 2) {  // lo is even: row parity picks the buffer
-        sweep_row<MB, VEC4, HALF, M0, 0>(S, D, H, bufs, lbufs, tour, n, i);
-        if (i + 1 < hi) sweep_row<MB, VEC4, HALF, M0, 1>(S, D, H, bufs, lbufs, tour, n, i + 1);
+        sweep_row<MB, VEC4, HALF, M0, 0>(S, D, H, bufs, lbufs, tour, n, i, end);
+        if (i + 1 < hi) sweep_row<MB, VEC4, HALF, M0, 1>(S, D, H, bufs, lbufs, tour, n, i + 1, end);
     }
     if constexpr (M0 + 1 < MB) {
-        if (hi < n - 2) sweep_phase<MB, VEC4, HALF, M0 + 1>(S, D, H, bufs, lbufs, tour, n);
+        if (hi < end) sweep_phase<MB, VEC4, HALF, M0 + 1>(S, D, H, bufs, lbufs, tour, n, begin, end);
     }
+}
+
+// The first row of wave w of a particle's two: the rows split so that each
+// wave gets about half of the triangle (row i has n - 3 - i columns, so the
+// split is near (n - 2)(1 - 1/sqrt 2), 75/256 of the rows), rounded down to
+// even; wave 2 starts at the end.
+__device__ inline int pair_first_row(int n, int w)
+{
+    const int rows = max(n - 2, 0);
+    return w == 0 ? 0 : w == 1 ? ((rows * 75) >> 8) & ~1 : rows;
 }
 
 }  // namespace
 
-template <int MB, bool VEC4, bool HALF>
+// W = 2 (16-bit rows only): two wavefronts share the particle, each sweeping
+// its own rows (pair_first_row) with its own row buffers; the candidate keys
+// and the exact minimum are combined through LDS, and the tour, held once,
+// changes between workgroup barriers.
+template <int MB, bool VEC4, bool HALF, int W = 1>
 __device__ __forceinline__ void twoopt_wave_body(const Inst &I, int p)
 {
+    static_assert(W == 1 || (W == 2 && HALF && VEC4), "two wavefronts per particle: 16-bit rows");
     constexpr int ST = WaveCfg<MB, VEC4>::STRIDE, GU = WaveCfg<MB, VEC4>::GUARD;
     const int32_t *__restrict__ D = I.D;
     const View st = I.st;
     const KParams kp = I.kp;
     Hdr *h = st.hdr;
     if (h->err || h->done || !h->ee_ran) return;
-    const int n = st.n, ns = st.ns, lane = threadIdx.x;
+    const int n = st.n, ns = st.ns, lane = threadIdx.x & 63, wave = W > 1 ? int(threadIdx.x >> 6) : 0;
+    // the wave's rows of the neighbourhood
+    const int begin = W > 1 ? pair_first_row(n, wave) : 0;
+    const int end = W > 1 ? pair_first_row(n, wave + 1) : n - 2;
+    // before the first barrier: thread 0 stores the new personal-best cost at the end
+    const int64_t fp_old = W > 1 ? st.FP[p] : 0;
     const uint16_t *__restrict__ H = st.H;
     const int hs = packed_stride(n);  // row stride of H
     // packed rows: the shift, the window T and the bound 2 (2^s - 1) on |rho|
@@ -539,19 +561,25 @@ __device__ __forceinline__ void twoopt_wave_body(const Inst &I, int p)
     const int window = shift == 0 ? 0 : shift == 1 ? 2 : 3;
     const int64_t rho = 2 * ((int64_t(1) << shift) - 1);
     extern __shared__ __align__(16) unsigned char smem[];
-    // [guard][buffer 0][guard][buffer 1][guard], buffer k at GU + k * ST
-    int32_t *bufs = reinterpret_cast<int32_t *>(smem) + GU;
-    lds_int *lbufs = (lds_int *)smem + GU;  // C-style: an address-space conversion
-    uint16_t *tour = reinterpret_cast<uint16_t *>(bufs + 2 * ST);
+    // per wave [guard][buffer 0][guard][buffer 1][guard], buffer k at GU + k * ST;
+    // then the tour
+    constexpr int WAVE_INTS = GU + 2 * ST;
+    int32_t *bufs = reinterpret_cast<int32_t *>(smem) + GU + wave * WAVE_INTS;
+    lds_int *lbufs = (lds_int *)smem + GU + wave * WAVE_INTS;  // C-style: an address-space conversion
+    uint16_t *tour = reinterpret_cast<uint16_t *>(reinterpret_cast<int32_t *>(smem) + W * WAVE_INTS);
     uint16_t *xg = st.X + size_t(p) * ns;
-    for (int k = lane; k < n; k += 64) tour[k] = xg[k];
+    for (int k = int(threadIdx.x); k < n; k += 64 * W) tour[k] = xg[k];
     compiler_fence();
+    if constexpr (W > 1) __syncthreads();
     int64_t F = st.F[p];
     int moves = 0, sweeps = 0;
     while (true) {
         ++sweeps;
         if (n < 4) break;
         SweepState<MB, VEC4> S;
+        S.best = kNone;
+        S.best_i = 0;
+        S.k1 = S.k2 = S.k3 = kNone;
         const unsigned char *slot_of = nullptr;
         if constexpr (HALF) {
             // the row buffers are free until the first row load below
@@ -570,15 +598,19 @@ __device__ __forceinline__ void twoopt_wave_body(const Inst &I, int p)
                 S.ne[m] = kPad;
             }
         }
-        // g <- D[x_0][x_c+1]: the first term of row 0, one column to the right
+        // g <- D[x_b][x_c+1]: the first term of the wave's first row b, one
+        // column to the right
         if constexpr (HALF) {
-            wait_lds();  // the placement's reads of the buffers are done
-            dma_half<WaveCfg<MB, VEC4>::RH>(H + size_t(tour[0]) * hs, S.src_chunk, lbufs + ST);
-            wait_vmem();
-            compiler_fence();
+            if (W == 1 || begin < end) {
+                wait_lds();  // the placement's reads of the buffers are done
+                dma_half<WaveCfg<MB, VEC4>::RH>(H + size_t(tour[begin]) * hs, S.src_chunk, lbufs + ST);
+                wait_vmem();
+                compiler_fence();
 #pragma unroll
-            for (int m = 0; m < MB; ++m) S.g[m] = lds_half(bufs + ST, S.off(m));
-            dma_half<WaveCfg<MB, VEC4>::RH>(H + size_t(tour[1]) * hs, S.src_chunk, lbufs);
+                for (int m = 0; m < MB; ++m) S.g[m] = lds_half(bufs + ST, S.off(m));
+                dma_half<WaveCfg<MB, VEC4>::RH>(H + size_t(tour[begin + 1]) * hs, S.src_chunk, lbufs);
+                sweep_phase<MB, VEC4, HALF, 0>(S, D, H, bufs, lbufs, tour, n, begin, end);
+            }
         } else if constexpr (kDma && VEC4) {
             wait_lds();  // earlier reads of both buffers are done
             dma_row<WaveCfg<MB, VEC4>::RV>(D + size_t(tour[0]) * n, n, lbufs + ST);
@@ -597,15 +629,20 @@ __device__ __forceinline__ void twoopt_wave_body(const Inst &I, int p)
             for (int k = 0; k < kPrefetch; ++k)
                 if (k + 1 < n) S.pipe[k].load(D + size_t(tour[k + 1]) * n, n);
         }
-        S.best = kNone;
-        S.best_i = 0;
-        S.k1 = S.k2 = S.k3 = kNone;
-        sweep_phase<MB, VEC4, HALF, 0>(S, D, H, bufs, lbufs, tour, n);
+        if constexpr (!HALF) sweep_phase<MB, VEC4, HALF, 0>(S, D, H, bufs, lbufs, tour, n, 0, n - 2);
         int dbest, bi, bj;
         if constexpr (HALF) {
             int kmin = S.k1;
 #pragma unroll
             for (int off = 32; off >= 1; off >>= 1) kmin = min(kmin, __shfl_xor(kmin, off, 64));
+            if constexpr (W > 1) {
+                __shared__ int red_key[W];
+                if (lane == 0) red_key[wave] = kmin;
+                __syncthreads();
+                kmin = red_key[0];
+#pragma unroll
+                for (int w = 1; w < W; ++w) kmin = min(kmin, red_key[w]);
+            }
             const int amin = key_value(kmin);
             if (int64_t(amin) * (int64_t(1) << shift) >= rho) break;  // no exchange improves
             const int lim = amin + window;
@@ -628,7 +665,7 @@ __device__ __forceinline__ void twoopt_wave_body(const Inst &I, int p)
                 }
             };
             if (__ballot(key_value(S.k3) <= lim)) {
-                for (int r = 0; r + 2 < n; ++r) exact_row(r);
+                for (int r = begin; r < end; ++r) exact_row(r);  // every row of the wave
             } else {
                 uint64_t rows = __ballot(key_value(S.k1) <= lim);
                 while (rows) {
@@ -643,7 +680,15 @@ __device__ __forceinline__ void twoopt_wave_body(const Inst &I, int p)
                     exact_row(__builtin_amdgcn_readlane(S.k2, k) & 1023);
                 }
             }
-            const uint64_t win = wave_min_u64(key);
+            uint64_t win = wave_min_u64(key);
+            if constexpr (W > 1) {
+                __shared__ uint64_t red_win[W];
+                if (lane == 0) red_win[wave] = win;
+                __syncthreads();
+                win = red_win[0];
+#pragma unroll
+                for (int w = 1; w < W; ++w) win = red_win[w] < win ? red_win[w] : win;
+            }
             dbest = int(uint32_t(win >> 32) - 0x80000000u);
             if (dbest >= 0) break;
             bi = int((win >> 16) & 0xffffu);
@@ -673,21 +718,22 @@ __device__ __forceinline__ void twoopt_wave_body(const Inst &I, int p)
         }
         // reverse tour[bi+1 .. bj]
         const int len = bj - bi;
-        for (int k = lane; k < len / 2; k += 64) {
+        for (int k = int(threadIdx.x); k < len / 2; k += 64 * W) {
             const uint16_t t0 = tour[bi + 1 + k];
             tour[bi + 1 + k] = tour[bj - k];
             tour[bj - k] = t0;
         }
         compiler_fence();
+        if constexpr (W > 1) __syncthreads();
         F += dbest;
         ++moves;
         if (kp.ee_max_moves > 0 && moves >= kp.ee_max_moves) break;
     }
-    for (int k = lane; k < n; k += 64) xg[k] = tour[k];
-    const bool better = F < st.FP[p];
+    for (int k = int(threadIdx.x); k < n; k += 64 * W) xg[k] = tour[k];
+    const bool better = F < (W > 1 ? fp_old : st.FP[p]);
     if (better)
-        for (int k = lane; k < n; k += 64) st.P[size_t(p) * ns + k] = tour[k];
-    if (lane == 0) {
+        for (int k = int(threadIdx.x); k < n; k += 64 * W) st.P[size_t(p) * ns + k] = tour[k];
+    if (threadIdx.x == 0) {
         st.F[p] = F;
         if (better) st.FP[p] = F;
         atomicAdd(reinterpret_cast<unsigned long long *>(&h->n_sweeps), (unsigned long long)sweeps);
@@ -711,13 +757,30 @@ __global__ __launch_bounds__(64, DPSO_2OPT_WAVES) void k_2opt_wave_batch(Batch B
     twoopt_wave_body<MB, VEC4, HALF>(I, p);
 }
 
-// Instances of several 16-bit row classes (up to MBMAX columns per lane) in
-// one launch: each workgroup runs the body of its own instance's class, the
-// code it runs in that class's launch, so instances of different n run side
-// by side instead of one class after another. The dynamic LDS is sized for
-// MBMAX; a smaller body uses the front of it.
-template <int MBMAX>
-__global__ __launch_bounds__(64, DPSO_2OPT_WAVES) void k_2opt_wave_mixed(Batch B)
+// Two wavefronts per particle, 16-bit rows (n > 128: MB = 4, 8, 16).
+template <int MB>
+__global__ __launch_bounds__(128, DPSO_2OPT_WAVES) void k_2opt_pair(Inst I)
+{
+    twoopt_wave_body<MB, true, true, 2>(I, int(blockIdx.x));
+}
+
+template <int MB>
+__global__ __launch_bounds__(128, DPSO_2OPT_WAVES) void k_2opt_pair_batch(Batch B)
+{
+    int p;
+    const int b = batch_item(B, int(blockIdx.x));
+    if (b < 0) return;
+    const Inst &I = batch_pick(B, b, p);
+    twoopt_wave_body<MB, true, true, 2>(I, p);
+}
+
+// Instances of several 16-bit row classes (up to MBMAX columns per lane, W
+// wavefronts per particle) in one launch: each workgroup runs the body of its
+// own instance's class, the code it runs in that class's launch, so instances
+// of different n run side by side instead of one class after another. The
+// dynamic LDS is sized for MBMAX; a smaller body uses the front of it.
+template <int MBMAX, int W>
+__global__ __launch_bounds__(64 * W, DPSO_2OPT_WAVES) void k_2opt_wave_mixed(Batch B)
 {
     int p;
     const int b = batch_item(B, int(blockIdx.x));
@@ -725,16 +788,20 @@ __global__ __launch_bounds__(64, DPSO_2OPT_WAVES) void k_2opt_wave_mixed(Batch B
     const Inst &I = batch_pick(B, b, p);
     const int n = I.st.n;  // uniform: the class bounds of exchange_class
     if constexpr (MBMAX >= 16) {
-        if (n > 512) return twoopt_wave_body<16, true, true>(I, p);
+        if (n > 512) return twoopt_wave_body<16, true, true, W>(I, p);
     }
     if constexpr (MBMAX >= 8) {
-        if (n > 256) return twoopt_wave_body<8, true, true>(I, p);
+        if (n > 256) return twoopt_wave_body<8, true, true, W>(I, p);
     }
-    if constexpr (MBMAX >= 4) {
-        if (n > 128) return twoopt_wave_body<4, true, true>(I, p);
+    if constexpr (W > 1) {
+        twoopt_wave_body<4, true, true, W>(I, p);  // pairs serve n > 128 only
+    } else {
+        if constexpr (MBMAX >= 4) {
+            if (n > 128) return twoopt_wave_body<4, true, true>(I, p);
+        }
+        if (n > 64) return twoopt_wave_body<2, true, true>(I, p);
+        twoopt_wave_body<1, true, true>(I, p);
     }
-    if (n > 64) return twoopt_wave_body<2, true, true>(I, p);
-    twoopt_wave_body<1, true, true>(I, p);
 }
 
 // Packed rows of one instance: the largest entry of D (into the header,
@@ -816,13 +883,29 @@ hipError_t launch_wave(const Inst *one, const Batch &B, int grid, int max_ns, hi
     return hipGetLastError();
 }
 
-template <int MBMAX>
+template <int MBMAX, int W>
 hipError_t launch_mixed(const Batch &B, int grid, int max_ns, hipStream_t s)
 {
-    const size_t lds = size_t(WaveCfg<MBMAX, true>::GUARD + 2 * WaveCfg<MBMAX, true>::STRIDE) * 4 + size_t(max_ns) * 2;
-    hipError_t e = allow_lds(k_2opt_wave_mixed<MBMAX>, lds);
+    const size_t lds = size_t(W) * (WaveCfg<MBMAX, true>::GUARD + 2 * WaveCfg<MBMAX, true>::STRIDE) * 4 +
+                       size_t(max_ns) * 2;
+    hipError_t e = allow_lds(k_2opt_wave_mixed<MBMAX, W>, lds);
     if (e != hipSuccess || grid <= 0) return e;
-    k_2opt_wave_mixed<MBMAX><<<grid, 64, lds, s>>>(B);
+    k_2opt_wave_mixed<MBMAX, W><<<grid, 64 * W, lds, s>>>(B);
+    return hipGetLastError();
+}
+
+template <int MB>
+hipError_t launch_pair(const Inst *one, const Batch &B, int grid, int max_ns, hipStream_t s)
+{
+    const size_t lds = size_t(2) * (WaveCfg<MB, true>::GUARD + 2 * WaveCfg<MB, true>::STRIDE) * 4 +
+                       size_t(max_ns) * 2;
+    hipError_t e = allow_lds(k_2opt_pair<MB>, lds);
+    if (e == hipSuccess) e = allow_lds(k_2opt_pair_batch<MB>, lds);
+    if (e != hipSuccess || grid <= 0) return e;
+    if (one)
+        k_2opt_pair<MB><<<grid, 128, lds, s>>>(*one);
+    else
+        k_2opt_pair_batch<MB><<<grid, 128, lds, s>>>(B);
     return hipGetLastError();
 }
 
@@ -857,14 +940,23 @@ hipError_t launch_class(int cls, const Inst *one, const Batch &B, int grid, int 
     case 12: return launch_wave<4, true, true>(one, B, grid, max_ns, s);
     case 13: return launch_wave<8, true, true>(one, B, grid, max_ns, s);
     case 14: return launch_wave<16, true, true>(one, B, grid, max_ns, s);
-    case 15: return launch_rows(one, B, grid, max_ns, s);
+    case 15: return launch_pair<4>(one, B, grid, max_ns, s);
+    case 16: return launch_pair<8>(one, B, grid, max_ns, s);
+    case 17: return launch_pair<16>(one, B, grid, max_ns, s);
+    case 18: return launch_rows(one, B, grid, max_ns, s);
     default: return launch_node_swap(one, B, grid, max_ns, s);
     }
 }
 
 constexpr int kFirstHalfClass = 10;  // 16-bit rows at 1, 2, 4, 8, 16 columns per lane
+constexpr int kFirstPairClass = 15;  // ... two wavefronts per particle, 4, 8, 16 columns per lane
+constexpr int kRowsClass = 18;       // one workgroup per particle, int32 rows
+static_assert(kExchangeClasses == kRowsClass + 2, "class table: the node-swap class last");
 
-bool half_class(int cls) { return cls >= kFirstHalfClass && cls < kFirstHalfClass + 5; }
+bool wave_half_class(int cls) { return cls >= kFirstHalfClass && cls < kFirstHalfClass + 5; }
+bool pair_class(int cls) { return cls >= kFirstPairClass && cls < kFirstPairClass + 3; }
+// classes that stage 16-bit rows (their set-up packs H)
+bool half_class(int cls) { return wave_half_class(cls) || pair_class(cls); }
 
 // blocks per instance for the packing kernels: ~16 entries per thread
 int pack_blocks(int n) { return int(std::min<int64_t>(1024, (int64_t(n) * packed_stride(n) + 4095) / 4096)); }
@@ -874,9 +966,11 @@ int pack_blocks(int n) { return int(std::min<int64_t>(1024, (int64_t(n) * packed
 int exchange_class(int n, const int32_t *D, int neighbourhood, int rows)
 {
     if (neighbourhood == DPSO_NB_NODE_SWAP) return kExchangeClasses - 1;
-    if (n > 1024 || rows == DPSO_ROWS_BLOCK) return kExchangeClasses - 2;
+    if (n > 1024 || rows == DPSO_ROWS_BLOCK) return kRowsClass;
     const int mb = n <= 64 ? 0 : n <= 128 ? 1 : n <= 256 ? 2 : n <= 512 ? 3 : 4;
-    if (kHalf && rows == DPSO_ROWS_U16 && packed_rows(n)) return kFirstHalfClass + mb;
+    if (kHalf && rows == DPSO_ROWS_U16_PAIR && packed_rows(n) && n > 128) return kFirstPairClass + mb - 2;
+    if (kHalf && (rows == DPSO_ROWS_U16 || rows == DPSO_ROWS_U16_PAIR) && packed_rows(n))
+        return kFirstHalfClass + mb;
     const bool vec4 = (n & 3) == 0 && (reinterpret_cast<uintptr_t>(D) & 15) == 0;
     return vec4 ? mb : 5 + mb;
 }
@@ -909,17 +1003,24 @@ hipError_t launch_batch_2opt(int cls, const Batch &items, int total, int max_ns,
     return launch_class(cls, nullptr, items, total, max_ns, s);
 }
 
-bool exchange_class_half(int cls) { return half_class(cls); }
+int exchange_merge_group(int cls) { return wave_half_class(cls) ? 1 : pair_class(cls) ? 2 : 0; }
 
 hipError_t launch_batch_2opt_mixed(int cls, const Batch &items, int total, int max_ns, hipStream_t s)
 {
-    if (!half_class(cls)) return hipErrorInvalidValue;
+    if (pair_class(cls)) {
+        switch (cls - kFirstPairClass) {
+        case 0: return launch_class(cls, nullptr, items, total, max_ns, s);  // the smallest: one body
+        case 1: return launch_mixed<8, 2>(items, total, max_ns, s);
+        default: return launch_mixed<16, 2>(items, total, max_ns, s);
+        }
+    }
+    if (!wave_half_class(cls)) return hipErrorInvalidValue;
     switch (cls - kFirstHalfClass) {
     case 0: return launch_class(cls, nullptr, items, total, max_ns, s);  // one column per lane: one body
-    case 1: return launch_mixed<2>(items, total, max_ns, s);
-    case 2: return launch_mixed<4>(items, total, max_ns, s);
-    case 3: return launch_mixed<8>(items, total, max_ns, s);
-    default: return launch_mixed<16>(items, total, max_ns, s);
+    case 1: return launch_mixed<2, 1>(items, total, max_ns, s);
+    case 2: return launch_mixed<4, 1>(items, total, max_ns, s);
+    case 3: return launch_mixed<8, 1>(items, total, max_ns, s);
+    default: return launch_mixed<16, 1>(items, total, max_ns, s);
     }
 }
 

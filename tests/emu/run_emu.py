@@ -365,7 +365,21 @@ def case_merge(emu: Emu) -> bool:
     """One batch with instances of every 16-bit row class (n = 9 ... 601, n not
     a multiple of 4 so small n take 16-bit rows too) beside int32, node-swap
     and row-per-workgroup ones, with the 16-bit row classes merged into one
-    launch and launched one after another."""
+    launch and launched one after another; then the same with two wavefronts
+    per particle above n = 128 (their classes merged apart from the
+    one-wavefront classes of the smaller n)."""
+    ok = True
+    for pair in (False, True):
+        L = emu.L
+        L.dpso_tuning_reset()
+        if pair:
+            force_tuning(emu, 256, 4)
+        ok &= _case_merge_once(emu)
+    emu.L.dpso_tuning_reset()
+    return ok
+
+
+def _case_merge_once(emu: Emu) -> bool:
     ok = True
     gens = 3
     L = emu.L

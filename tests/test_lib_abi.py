@@ -147,11 +147,12 @@ def test_tuning_table(dp):
         # 64 threads serve n up to 1024, 128 up to 2048; the wavefront exchange n up to 1024
         dp.tuning_set(1024, 64, {"move_threads": 64})
         for n, cfg in ((1025, {"move_threads": 64}), (2049, {"move_threads": 128}),
-                       (1500, {"exchange_rows": dp.ROWS_U16}), (1500, {"exchange_rows": dp.ROWS_I32})):
+                       (1500, {"exchange_rows": dp.ROWS_U16}), (1500, {"exchange_rows": dp.ROWS_I32}),
+                       (1500, {"exchange_rows": dp.ROWS_U16_PAIR})):
             with pytest.raises(dp.DpsoError) as e:
                 dp.tuning_set(n, 64, cfg)
             assert e.value.status == dp.E_RANGE, (n, cfg)
-        for cfg in ({"move_threads": 32}, {"move_threads": 512}, {"exchange_rows": 4}, {"exchange_rows": -1}):
+        for cfg in ({"move_threads": 32}, {"move_threads": 512}, {"exchange_rows": 5}, {"exchange_rows": -1}):
             with pytest.raises(dp.DpsoError) as e:
                 dp.tuning_set(100, 64, cfg)
             assert e.value.status == dp.E_INVAL, cfg
@@ -164,6 +165,11 @@ def test_tuning_table(dp):
         dp.tuning_set(6, 64, {"exchange_rows": dp.ROWS_U16})
         assert dp.tuning_get(8, 64)["exchange_rows"] == dp.ROWS_U16
         assert dp.tuning_get(7, 64)["exchange_rows"] == dp.ROWS_I32
+        # two wavefronts per particle split n > 128; smaller n of a bucket take one
+        dp.tuning_set(200, 64, {"exchange_rows": dp.ROWS_U16_PAIR})
+        assert dp.tuning_get(129, 64)["exchange_rows"] == dp.ROWS_U16_PAIR
+        dp.tuning_set(100, 64, {"exchange_rows": dp.ROWS_U16_PAIR})
+        assert dp.tuning_get(100, 64)["exchange_rows"] == dp.ROWS_U16
         # the batch order
         assert dp.batch_order_get() == dp.ORDER_LPT
         for o in (dp.ORDER_INDEX, dp.ORDER_XCD, dp.ORDER_LPT):
