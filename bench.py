@@ -513,7 +513,7 @@ def main():
                     help="repetitions of the timed run (fresh swarm each); the median is reported")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the other workloads (n=30, n=200, batched, served) in the default line")
-    ap.add_argument("--extra-serve", type=int, default=1000,
+    ap.add_argument("--extra-serve", type=int, default=3000,
                     help="requests of the served run in the default line")
     ap.add_argument("--batch", type=int, default=0,
                     help="run the batched workload with this many instances instead")
@@ -717,7 +717,7 @@ def main():
     if not args.no_extras:
         line["workloads"] = {"facade30": small_workload(1, 5), "bridge200": small_workload(2, 5)}
         line["batched"] = compact_batch(bench_batch(256, 500))
-        line["served"] = compact_serve(bench_serve(args.extra_serve, 50.0, args.extra_serve // 5, 2048,
+        line["served"] = compact_serve(bench_serve(args.extra_serve, 50.0, min(200, args.extra_serve // 4), 2048,
                                                    chunk=args.serve_chunk))
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
