@@ -191,10 +191,9 @@ bool host_velocity_tours(const uint16_t *pairs, int len, int n, uint16_t *from, 
 // prefix tables (per particle, per instance), and for every move class and
 // every edge-exchange class the descriptors of its members with their
 // particle prefix.
-// Move classes: threads per particle 64 / 128 / 256. A class takes the
-// positions per thread of its largest member (one launch per class: in a
-// small batch several narrow launches one after another cost more than the
-// unrolled positions past a short tour's end).
+// Move classes: threads per particle 64 / 128 / 256, one launch each; in it
+// every member runs at its own positions per thread (the move's mixed batch
+// kernel), not at its class's largest.
 constexpr int kMoveClasses = 3;
 
 int move_class(int tpb) { return tpb == 64 ? 0 : tpb == 128 ? 1 : 2; }

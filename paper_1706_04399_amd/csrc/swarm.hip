@@ -892,6 +892,34 @@ __global__ __launch_bounds__(TPB) void k_move_batch(Batch B)
     move_body<TPB, EPT>(I, item);
 }
 
+// A batch whose instances need different positions per thread (up to
+// EPTMAX) in one launch: each workgroup runs the body at its own instance's
+// ceil(ns / TPB) rounded up to a power of two, the layout a launch of that
+// instance alone takes, instead of the largest instance's. The dynamic LDS
+// is sized for the largest.
+template <int TPB, int EPTMAX>
+__global__ __launch_bounds__(TPB) void k_move_batch_mixed(Batch B)
+{
+    const int b = batch_item(B, int(blockIdx.x));
+    if (b < 0) return;
+    int item;
+    const Inst &I = batch_pick(B, b, item);
+    const int ept = (I.st.ns + TPB - 1) / TPB;  // uniform
+    if constexpr (EPTMAX >= 16) {
+        if (ept > 8) return move_body<TPB, 16>(I, item);
+    }
+    if constexpr (EPTMAX >= 8) {
+        if (ept > 4) return move_body<TPB, 8>(I, item);
+    }
+    if constexpr (EPTMAX >= 4) {
+        if (ept > 2) return move_body<TPB, 4>(I, item);
+    }
+    if constexpr (EPTMAX >= 2) {
+        if (ept > 1) return move_body<TPB, 2>(I, item);
+    }
+    move_body<TPB, 1>(I, item);
+}
+
 // ---------------------------------------------------------------- launchers
 
 size_t init_lds_bytes(int ns) { return size_t(ns) * 2 + size_t(ns) * 14; }
@@ -955,12 +983,13 @@ namespace {
 template <int TPB>
 hipError_t launch_move_tpb(const Target &t, size_t lds, hipStream_t s)
 {
+    // a batch takes the mixed kernel: each instance at its own positions per thread
     const int ept = (t.max_ns + TPB - 1) / TPB;
     if (ept <= 1) return launch(k_move<TPB, 1>, k_move_batch<TPB, 1>, t, true, TPB, lds, s);
-    if (ept <= 2) return launch(k_move<TPB, 2>, k_move_batch<TPB, 2>, t, true, TPB, lds, s);
-    if (ept <= 4) return launch(k_move<TPB, 4>, k_move_batch<TPB, 4>, t, true, TPB, lds, s);
-    if (ept <= 8) return launch(k_move<TPB, 8>, k_move_batch<TPB, 8>, t, true, TPB, lds, s);
-    if (ept <= 16) return launch(k_move<TPB, 16>, k_move_batch<TPB, 16>, t, true, TPB, lds, s);
+    if (ept <= 2) return launch(k_move<TPB, 2>, k_move_batch_mixed<TPB, 2>, t, true, TPB, lds, s);
+    if (ept <= 4) return launch(k_move<TPB, 4>, k_move_batch_mixed<TPB, 4>, t, true, TPB, lds, s);
+    if (ept <= 8) return launch(k_move<TPB, 8>, k_move_batch_mixed<TPB, 8>, t, true, TPB, lds, s);
+    if (ept <= 16) return launch(k_move<TPB, 16>, k_move_batch_mixed<TPB, 16>, t, true, TPB, lds, s);
     return hipErrorInvalidConfiguration;  // more than 16 positions per thread
 }
 
