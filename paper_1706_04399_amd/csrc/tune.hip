@@ -59,7 +59,11 @@ int tune_bucket_p(int64_t particles)
 // batches, whose move and exchange classes run one after another — every
 // n from 8 to 1024 takes 16-bit rows, which keeps one exchange class per
 // column count (the batched workload: 320 solves/s against 290 with int32
-// rows for the multiples of 4). The move runs one wavefront per particle for
+// rows for the multiples of 4). Among at most 1024 particles, which leave
+// most SIMDs idle, the other n above 128 take 16-bit rows with two wavefronts
+// per particle (n = 800, swarm 512: 3.33 against 3.80 ms for 12 generations;
+// served re-planning p99 132 against 140 ms), all in one merge group. The move
+// runs one wavefront per particle for
 // a lone swarm of at most 128 (the cheapest barriers) and, among more than
 // 8192 particles, for n <= 512 (the GPU is full whatever the width, and
 // narrow blocks waste no lanes); 256 threads otherwise.
@@ -75,7 +79,8 @@ Tune default_tuning(int n, int64_t particles)
     else
         t.move_threads = 256;
     const bool i32 = !packed_rows(n) || (particles <= 1024 && aligned && n <= 256);
-    t.exchange_rows = n > 1024 ? DPSO_ROWS_BLOCK : i32 ? DPSO_ROWS_I32 : DPSO_ROWS_U16;
+    const bool pair = particles <= 1024 && n > 128;
+    t.exchange_rows = n > 1024 ? DPSO_ROWS_BLOCK : i32 ? DPSO_ROWS_I32 : pair ? DPSO_ROWS_U16_PAIR : DPSO_ROWS_U16;
     return t;
 }
 

@@ -757,15 +757,19 @@ __global__ __launch_bounds__(64, DPSO_2OPT_WAVES) void k_2opt_wave_batch(Batch B
     twoopt_wave_body<MB, VEC4, HALF>(I, p);
 }
 
-// Two wavefronts per particle, 16-bit rows (n > 128: MB = 4, 8, 16).
+// Two wavefronts per particle, 16-bit rows (n > 128: MB = 4, 8, 16). They are
+// for launches that leave SIMDs idle, so they trade occupancy for registers:
+// at least two waves per SIMD (256 VGPRs), where four would make the row loop
+// spill.
+#define DPSO_PAIR_WAVES 2
 template <int MB>
-__global__ __launch_bounds__(128, DPSO_2OPT_WAVES) void k_2opt_pair(Inst I)
+__global__ __launch_bounds__(128, DPSO_PAIR_WAVES) void k_2opt_pair(Inst I)
 {
     twoopt_wave_body<MB, true, true, 2>(I, int(blockIdx.x));
 }
 
 template <int MB>
-__global__ __launch_bounds__(128, DPSO_2OPT_WAVES) void k_2opt_pair_batch(Batch B)
+__global__ __launch_bounds__(128, DPSO_PAIR_WAVES) void k_2opt_pair_batch(Batch B)
 {
     int p;
     const int b = batch_item(B, int(blockIdx.x));
@@ -780,7 +784,7 @@ __global__ __launch_bounds__(128, DPSO_2OPT_WAVES) void k_2opt_pair_batch(Batch 
 // of different n run side by side instead of one class after another. The
 // dynamic LDS is sized for MBMAX; a smaller body uses the front of it.
 template <int MBMAX, int W>
-__global__ __launch_bounds__(64 * W, DPSO_2OPT_WAVES) void k_2opt_wave_mixed(Batch B)
+__global__ __launch_bounds__(64 * W, W > 1 ? DPSO_PAIR_WAVES : DPSO_2OPT_WAVES) void k_2opt_wave_mixed(Batch B)
 {
     int p;
     const int b = batch_item(B, int(blockIdx.x));

@@ -19,14 +19,16 @@ def test_more_than_one_gpu_is_refused():
 
 
 @pytest.mark.parametrize("n,name", [
-    (1000, "k_2opt_wave<16, true, true>"),    # 16-bit rows (n > 256 among <= 1024 particles)
-    (1024, "k_2opt_wave<16, true, true>"),
-    (1021, "k_2opt_wave<16, true, true>"),    # padded 16-bit rows
-    (516, "k_2opt_wave<16, true, true>"),
-    (512, "k_2opt_wave<8, true, true>"),
-    (260, "k_2opt_wave<8, true, true>"),
+    (1000, "k_2opt_pair<16>"),                # 16-bit rows, two wavefronts (n > 128 among <= 1024 particles)
+    (1024, "k_2opt_pair<16>"),
+    (1021, "k_2opt_pair<16>"),                # padded 16-bit rows
+    (516, "k_2opt_pair<16>"),
+    (512, "k_2opt_pair<8>"),
+    (260, "k_2opt_pair<8>"),
     (256, "k_2opt_wave<4, true, false>"),     # int32 rows straight into LDS (n <= 256, n % 4 == 0)
-    (255, "k_2opt_wave<4, true, true>"),      # rows of D off 16 bytes: 16-bit copy
+    (255, "k_2opt_pair<4>"),                  # rows of D off 16 bytes: 16-bit copy
+    (100, "k_2opt_wave<2, true, false>"),
+    (101, "k_2opt_wave<2, true, true>"),      # n <= 128: one wavefront
     (64, "k_2opt_wave<1, true, false>"),
     (9, "k_2opt_wave<1, true, true>"),
     (5, "k_2opt_wave<1, false, false>"),      # below 8: int32 rows through registers
@@ -38,4 +40,17 @@ def test_exchange_kernel_name_follows_the_default_rows(n, name):
     from paper_1706_04399_amd import dpso
     dpso.tuning_reset()
     rows = dpso.tuning_get(n, 1024)["exchange_rows"]
+    assert bench.exchange_kernel_name(n, rows) == name
+
+
+@pytest.mark.parametrize("n,name", [
+    (1000, "k_2opt_wave<16, true, true>"),    # the headline: 16-bit rows, one wavefront
+    (516, "k_2opt_wave<16, true, true>"),
+    (260, "k_2opt_wave<8, true, true>"),
+    (256, "k_2opt_wave<4, true, true>"),      # above 1024 particles every n >= 8 takes 16-bit rows
+])
+def test_exchange_kernel_name_among_many_particles(n, name):
+    from paper_1706_04399_amd import dpso
+    dpso.tuning_reset()
+    rows = dpso.tuning_get(n, 4096)["exchange_rows"]
     assert bench.exchange_kernel_name(n, rows) == name

@@ -120,7 +120,11 @@ def test_tuning_table(dp):
     assert dp.tuning_get(200, 1025) == {"move_threads": 256, "exchange_rows": dp.ROWS_U16}
     assert dp.tuning_get(200, 65536) == {"move_threads": 64, "exchange_rows": dp.ROWS_U16}
     assert dp.tuning_get(384, 65536) == {"move_threads": 64, "exchange_rows": dp.ROWS_U16}
-    assert dp.tuning_get(384, 512) == {"move_threads": 256, "exchange_rows": dp.ROWS_U16}
+    assert dp.tuning_get(384, 512) == {"move_threads": 256, "exchange_rows": dp.ROWS_U16_PAIR}
+    assert dp.tuning_get(129, 1024)["exchange_rows"] == dp.ROWS_U16_PAIR
+    assert dp.tuning_get(128, 1024)["exchange_rows"] == dp.ROWS_I32
+    assert dp.tuning_get(127, 1024)["exchange_rows"] == dp.ROWS_U16
+    assert dp.tuning_get(384, 1025)["exchange_rows"] == dp.ROWS_U16
     assert dp.tuning_get(516, 65536) == {"move_threads": 256, "exchange_rows": dp.ROWS_U16}
     assert dp.tuning_get(2000, 8) == {"move_threads": 256, "exchange_rows": dp.ROWS_BLOCK}
     assert dp.tuning_get(2000, 64)["move_threads"] == 256     # 64 threads serve n <= 1024 only
