@@ -39,13 +39,15 @@ KERNEL_SRC = os.path.join(ROOT, "paper_1706_04399_amd", "csrc", "twoopt.hip")
 def exchange_kernel_name(n: int, rows: int) -> str:
     """The edge-exchange kernel an instance of n runs with the row form
     `rows` (1: 16-bit, 2: int32, 3: one workgroup per particle, 4: 16-bit,
-    two wavefronts per particle above n = 128):
+    two wavefronts per particle above n = 128, 5: four above n = 256):
     <columns per lane / 64, rows go straight into LDS, 16-bit rows>; 16-bit
     rows are padded to 16 bytes, so they always go straight into LDS."""
     if rows == 3 or n > 1024:
         return "k_2opt_rows"
     mb = next(m for m in (1, 2, 4, 8, 16) if n <= 64 * m)
-    if rows == 4 and n > 128:
+    if rows == 5 and n > 256:
+        return f"k_2opt_quad<{mb}>"
+    if rows in (4, 5) and n > 128:
         return f"k_2opt_pair<{mb}>"
     packed = rows == 1
     direct = packed or n % 4 == 0

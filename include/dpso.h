@@ -401,13 +401,16 @@ dpso_status dpso_import_state(void *d_state, size_t state_bytes, int32_t n, int3
 #define DPSO_ROWS_U16_PAIR 4 /* 16-bit rows, two wavefronts per particle, each
                                 sweeping about half of the neighbourhood (for
                                 128 < n <= 1024; smaller n take DPSO_ROWS_U16) */
+#define DPSO_ROWS_U16_QUAD 5 /* 16-bit rows, four wavefronts per particle (for
+                                256 < n <= 1024; smaller n take DPSO_ROWS_U16_PAIR) */
 
 typedef struct {
     int32_t move_threads;  /* 64, 128 or 256 threads per particle (0: default);
                               n must be at most 16 * move_threads               */
     int32_t exchange_rows; /* DPSO_ROWS_*; a form that does not serve an n of the
-                              bucket falls back: U16_PAIR to U16 up to n = 128,
-                              U16 below 8 to the default                        */
+                              bucket falls back: U16_QUAD to U16_PAIR up to
+                              n = 256, U16_PAIR to U16 up to n = 128, U16 below 8
+                              to the default                                    */
 } dpso_tuning;
 
 /* The configuration the library uses for an instance of n viewpoints among

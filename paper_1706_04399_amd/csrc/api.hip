@@ -347,9 +347,9 @@ dpso_status plan_batch(const dpso_batch_item *items, int32_t count, void *d_work
         }
     }
     // a batch small enough merges the 16-bit row classes of each merge group
-    // (one or two wavefronts per particle) into the group's largest (one
+    // (one, two or four wavefronts per particle) into the group's largest (one
     // launch, each instance with its own class's code)
-    for (int group = 1; group <= 2 && total <= dpso::batch_merge(); ++group) {
+    for (int group = 1; group <= 3 && total <= dpso::batch_merge(); ++group) {
         int top = -1, classes = 0;
         for (int c = 0; c < dpso::kExchangeClasses; ++c)
             if (dpso::exchange_merge_group(c) == group && !cls_members[c].empty()) {
@@ -849,10 +849,11 @@ dpso_status dpso_autotune(const int32_t *d_dist, int32_t n, const dpso_params *p
     const bool exchange = params->ee_trigger != DPSO_EE_OFF && params->ee_neighbourhood == DPSO_NB_TWO_OPT;
     if (exchange) {
         const int tpb = done[best].config.move_threads;
-        for (int rows : {DPSO_ROWS_U16, DPSO_ROWS_I32, DPSO_ROWS_BLOCK, DPSO_ROWS_U16_PAIR}) {
+        for (int rows : {DPSO_ROWS_U16, DPSO_ROWS_I32, DPSO_ROWS_BLOCK, DPSO_ROWS_U16_PAIR, DPSO_ROWS_U16_QUAD}) {
             if (rows == dflt.exchange_rows) continue;
             if (rows == DPSO_ROWS_U16 && !dpso::packed_rows(n)) continue;
             if (rows == DPSO_ROWS_U16_PAIR && !(dpso::packed_rows(n) && n > 128)) continue;
+            if (rows == DPSO_ROWS_U16_QUAD && !(dpso::packed_rows(n) && n > 256)) continue;
             if (rows == DPSO_ROWS_I32 && n > 1024) continue;
             // an n off 16 bytes takes 16-bit rows for int32 ones: the same kernel
             if (rows == DPSO_ROWS_I32 && (n & 3) != 0 && dpso::packed_rows(n)) continue;

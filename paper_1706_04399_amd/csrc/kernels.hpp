@@ -35,11 +35,11 @@ hipError_t launch_batch_end(const Batch &items, const Batch &instances, int tota
 // (columns held per lane), on the row form of the configuration and on the
 // alignment of D (exchange_class, tune.hpp); instances of one class share a
 // launch. The last class is the node-swap neighbourhood.
-constexpr int kExchangeClasses = 20;
+constexpr int kExchangeClasses = 22;
 hipError_t launch_2opt(const Inst &I, int cls, hipStream_t s);
 hipError_t launch_batch_2opt(int cls, const Batch &items, int total, int max_ns, hipStream_t s);
 // Classes that stage 16-bit rows can share a launch with the other classes
-// of their merge group (1: one wavefront per particle, 2: two; 0: none):
+// of their merge group (1: one wavefront per particle, 2: two, 3: four; 0: none):
 // launch_batch_2opt_mixed runs `items`, instances of class `cls` or of
 // smaller classes of its group, in one launch, each with its own class's
 // body.

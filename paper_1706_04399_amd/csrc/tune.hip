@@ -61,8 +61,10 @@ int tune_bucket_p(int64_t particles)
 // column count (the batched workload: 320 solves/s against 290 with int32
 // rows for the multiples of 4). Among at most 1024 particles, which leave
 // most SIMDs idle, the other n above 128 take 16-bit rows with two wavefronts
-// per particle (n = 800, swarm 512: 3.33 against 3.80 ms for 12 generations;
-// served re-planning p99 132 against 140 ms), all in one merge group. The move
+// per particle, and among at most 512 those above 256 with four (n = 800,
+// swarm 512: 2.75 ms for 12 generations with four, 3.30 with two, 3.82 with
+// one; served re-planning p99 126 ms against 135 with pairs only and 140 with
+// one wavefront). The move
 // runs one wavefront per particle for
 // a lone swarm of at most 128 (the cheapest barriers) and, among more than
 // 8192 particles, for n <= 512 (the GPU is full whatever the width, and
@@ -79,8 +81,12 @@ Tune default_tuning(int n, int64_t particles)
     else
         t.move_threads = 256;
     const bool i32 = !packed_rows(n) || (particles <= 1024 && aligned && n <= 256);
-    const bool pair = particles <= 1024 && n > 128;
-    t.exchange_rows = n > 1024 ? DPSO_ROWS_BLOCK : i32 ? DPSO_ROWS_I32 : pair ? DPSO_ROWS_U16_PAIR : DPSO_ROWS_U16;
+    const bool quad = particles <= 512 && n > 256, pair = particles <= 1024 && n > 128;
+    t.exchange_rows = n > 1024 ? DPSO_ROWS_BLOCK
+                      : i32    ? DPSO_ROWS_I32
+                      : quad   ? DPSO_ROWS_U16_QUAD
+                      : pair   ? DPSO_ROWS_U16_PAIR
+                               : DPSO_ROWS_U16;
     return t;
 }
 
@@ -94,11 +100,14 @@ Tune resolve_tuning(Tune t, int n, int64_t particles)
     const int ns = (n + 63) & ~63;
     if (!move_threads_ok(t.move_threads, ns)) t.move_threads = d.move_threads;
     if (t.exchange_rows == DPSO_ROWS_I32 && (n & 3) != 0 && packed_rows(n)) t.exchange_rows = DPSO_ROWS_U16;
-    // two wavefronts per particle split at least 128 rows; smaller n take one
+    // four wavefronts per particle split at least 256 rows, two at least 128;
+    // smaller n take fewer
+    if (t.exchange_rows == DPSO_ROWS_U16_QUAD && packed_rows(n) && n <= 256) t.exchange_rows = DPSO_ROWS_U16_PAIR;
     if (t.exchange_rows == DPSO_ROWS_U16_PAIR && packed_rows(n) && n <= 128) t.exchange_rows = DPSO_ROWS_U16;
     const bool ok = t.exchange_rows == DPSO_ROWS_BLOCK || (t.exchange_rows == DPSO_ROWS_I32 && n <= 1024) ||
                     (t.exchange_rows == DPSO_ROWS_U16 && packed_rows(n)) ||
-                    (t.exchange_rows == DPSO_ROWS_U16_PAIR && packed_rows(n) && n > 128);
+                    (t.exchange_rows == DPSO_ROWS_U16_PAIR && packed_rows(n) && n > 128) ||
+                    (t.exchange_rows == DPSO_ROWS_U16_QUAD && packed_rows(n) && n > 256);
     if (!ok) t.exchange_rows = d.exchange_rows;
     return t;
 }
@@ -154,14 +163,14 @@ dpso_status dpso_tuning_set(int32_t n, int32_t particles, const dpso_tuning *t)
     if (t) {
         if (t->move_threads != 0 && t->move_threads != 64 && t->move_threads != 128 && t->move_threads != 256)
             return fail(DPSO_E_INVAL, "move_threads = %d is not 0, 64, 128 or 256", t->move_threads);
-        if (t->exchange_rows < DPSO_ROWS_AUTO || t->exchange_rows > DPSO_ROWS_U16_PAIR)
+        if (t->exchange_rows < DPSO_ROWS_AUTO || t->exchange_rows > DPSO_ROWS_U16_QUAD)
             return fail(DPSO_E_INVAL, "exchange_rows = %d is not a DPSO_ROWS_* value", t->exchange_rows);
         const int top = dpso::bucket_max_n(bn), ns = (top + 63) & ~63;
         if (t->move_threads != 0 && !dpso::move_threads_ok(t->move_threads, ns))
             return fail(DPSO_E_RANGE, "%d threads per particle cannot serve n = %d (at most 16 positions each)",
                         t->move_threads, top);
         if ((t->exchange_rows == DPSO_ROWS_U16 || t->exchange_rows == DPSO_ROWS_I32 ||
-             t->exchange_rows == DPSO_ROWS_U16_PAIR) && n > 1024)
+             t->exchange_rows == DPSO_ROWS_U16_PAIR || t->exchange_rows == DPSO_ROWS_U16_QUAD) && n > 1024)
             return fail(DPSO_E_RANGE, "the wavefront exchange serves n up to 1024");
         e.move_threads = t->move_threads;
         e.exchange_rows = t->exchange_rows;

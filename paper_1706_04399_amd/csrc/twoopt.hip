@@ -522,26 +522,31 @@ __device__ __forceinline__ void sweep_phase(SweepState<MB, VEC4> &S, const int32
     }
 }
 
-// The first row of wave w of a particle's two: the rows split so that each
-// wave gets about half of the triangle (row i has n - 3 - i columns, so the
-// split is near (n - 2)(1 - 1/sqrt 2), 75/256 of the rows), rounded down to
-// even; wave 2 starts at the end.
-__device__ inline int pair_first_row(int n, int w)
+// The first row of wave w of the W (2 or 4) sharing a particle: the rows
+// split so that each wave gets about 1/W of the triangle (row i has n - 3 - i
+// columns, so wave w starts near (n - 2)(1 - sqrt((W - w) / W)): 75/256 of the
+// rows for two waves; 34/256, 75/256 and 128/256 for four), rounded down to
+// even; wave W starts at the end.
+template <int W>
+__device__ inline int wave_first_row(int n, int w)
 {
     const int rows = max(n - 2, 0);
-    return w == 0 ? 0 : w == 1 ? ((rows * 75) >> 8) & ~1 : rows;
+    if (w <= 0) return 0;
+    if (w >= W) return rows;
+    const int f = W == 2 ? 75 : w == 1 ? 34 : w == 2 ? 75 : 128;
+    return ((rows * f) >> 8) & ~1;
 }
 
 }  // namespace
 
-// W = 2 (16-bit rows only): two wavefronts share the particle, each sweeping
-// its own rows (pair_first_row) with its own row buffers; the candidate keys
-// and the exact minimum are combined through LDS, and the tour, held once,
-// changes between workgroup barriers.
+// W = 2 or 4 (16-bit rows only): W wavefronts share the particle, each
+// sweeping its own rows (wave_first_row) with its own row buffers; the
+// candidate keys and the exact minimum are combined through LDS, and the tour,
+// held once, changes between workgroup barriers.
 template <int MB, bool VEC4, bool HALF, int W = 1>
 __device__ __forceinline__ void twoopt_wave_body(const Inst &I, int p)
 {
-    static_assert(W == 1 || (W == 2 && HALF && VEC4), "two wavefronts per particle: 16-bit rows");
+    static_assert(W == 1 || ((W == 2 || W == 4) && HALF && VEC4), "wavefronts per particle: 16-bit rows");
     constexpr int ST = WaveCfg<MB, VEC4>::STRIDE, GU = WaveCfg<MB, VEC4>::GUARD;
     const int32_t *__restrict__ D = I.D;
     const View st = I.st;
@@ -550,8 +555,8 @@ __device__ __forceinline__ void twoopt_wave_body(const Inst &I, int p)
     if (h->err || h->done || !h->ee_ran) return;
     const int n = st.n, ns = st.ns, lane = threadIdx.x & 63, wave = W > 1 ? int(threadIdx.x >> 6) : 0;
     // the wave's rows of the neighbourhood
-    const int begin = W > 1 ? pair_first_row(n, wave) : 0;
-    const int end = W > 1 ? pair_first_row(n, wave + 1) : n - 2;
+    const int begin = W > 1 ? wave_first_row<W>(n, wave) : 0;
+    const int end = W > 1 ? wave_first_row<W>(n, wave + 1) : n - 2;
     // before the first barrier: thread 0 stores the new personal-best cost at the end
     const int64_t fp_old = W > 1 ? st.FP[p] : 0;
     const uint16_t *__restrict__ H = st.H;
@@ -778,6 +783,24 @@ __global__ __launch_bounds__(128, DPSO_PAIR_WAVES) void k_2opt_pair_batch(Batch 
     twoopt_wave_body<MB, true, true, 2>(I, p);
 }
 
+// Four wavefronts per particle, 16-bit rows (n > 256: MB = 8, 16), for
+// launches of a few hundred particles.
+template <int MB>
+__global__ __launch_bounds__(256, DPSO_PAIR_WAVES) void k_2opt_quad(Inst I)
+{
+    twoopt_wave_body<MB, true, true, 4>(I, int(blockIdx.x));
+}
+
+template <int MB>
+__global__ __launch_bounds__(256, DPSO_PAIR_WAVES) void k_2opt_quad_batch(Batch B)
+{
+    int p;
+    const int b = batch_item(B, int(blockIdx.x));
+    if (b < 0) return;
+    const Inst &I = batch_pick(B, b, p);
+    twoopt_wave_body<MB, true, true, 4>(I, p);
+}
+
 // Instances of several 16-bit row classes (up to MBMAX columns per lane, W
 // wavefronts per particle) in one launch: each workgroup runs the body of its
 // own instance's class, the code it runs in that class's launch, so instances
@@ -797,7 +820,9 @@ __global__ __launch_bounds__(64 * W, W > 1 ? DPSO_PAIR_WAVES : DPSO_2OPT_WAVES) 
     if constexpr (MBMAX >= 8) {
         if (n > 256) return twoopt_wave_body<8, true, true, W>(I, p);
     }
-    if constexpr (W > 1) {
+    if constexpr (W == 4) {
+        twoopt_wave_body<8, true, true, 4>(I, p);  // quads serve n > 256 only
+    } else if constexpr (W > 1) {
         twoopt_wave_body<4, true, true, W>(I, p);  // pairs serve n > 128 only
     } else {
         if constexpr (MBMAX >= 4) {
@@ -899,6 +924,21 @@ hipError_t launch_mixed(const Batch &B, int grid, int max_ns, hipStream_t s)
 }
 
 template <int MB>
+hipError_t launch_quad(const Inst *one, const Batch &B, int grid, int max_ns, hipStream_t s)
+{
+    const size_t lds = size_t(4) * (WaveCfg<MB, true>::GUARD + 2 * WaveCfg<MB, true>::STRIDE) * 4 +
+                       size_t(max_ns) * 2;
+    hipError_t e = allow_lds(k_2opt_quad<MB>, lds);
+    if (e == hipSuccess) e = allow_lds(k_2opt_quad_batch<MB>, lds);
+    if (e != hipSuccess || grid <= 0) return e;
+    if (one)
+        k_2opt_quad<MB><<<grid, 256, lds, s>>>(*one);
+    else
+        k_2opt_quad_batch<MB><<<grid, 256, lds, s>>>(B);
+    return hipGetLastError();
+}
+
+template <int MB>
 hipError_t launch_pair(const Inst *one, const Batch &B, int grid, int max_ns, hipStream_t s)
 {
     const size_t lds = size_t(2) * (WaveCfg<MB, true>::GUARD + 2 * WaveCfg<MB, true>::STRIDE) * 4 +
@@ -947,20 +987,24 @@ hipError_t launch_class(int cls, const Inst *one, const Batch &B, int grid, int 
     case 15: return launch_pair<4>(one, B, grid, max_ns, s);
     case 16: return launch_pair<8>(one, B, grid, max_ns, s);
     case 17: return launch_pair<16>(one, B, grid, max_ns, s);
-    case 18: return launch_rows(one, B, grid, max_ns, s);
+    case 18: return launch_quad<8>(one, B, grid, max_ns, s);
+    case 19: return launch_quad<16>(one, B, grid, max_ns, s);
+    case 20: return launch_rows(one, B, grid, max_ns, s);
     default: return launch_node_swap(one, B, grid, max_ns, s);
     }
 }
 
 constexpr int kFirstHalfClass = 10;  // 16-bit rows at 1, 2, 4, 8, 16 columns per lane
 constexpr int kFirstPairClass = 15;  // ... two wavefronts per particle, 4, 8, 16 columns per lane
-constexpr int kRowsClass = 18;       // one workgroup per particle, int32 rows
+constexpr int kFirstQuadClass = 18;  // ... four wavefronts per particle, 8, 16 columns per lane
+constexpr int kRowsClass = 20;       // one workgroup per particle, int32 rows
 static_assert(kExchangeClasses == kRowsClass + 2, "class table: the node-swap class last");
 
 bool wave_half_class(int cls) { return cls >= kFirstHalfClass && cls < kFirstHalfClass + 5; }
 bool pair_class(int cls) { return cls >= kFirstPairClass && cls < kFirstPairClass + 3; }
+bool quad_class(int cls) { return cls >= kFirstQuadClass && cls < kFirstQuadClass + 2; }
 // classes that stage 16-bit rows (their set-up packs H)
-bool half_class(int cls) { return wave_half_class(cls) || pair_class(cls); }
+bool half_class(int cls) { return wave_half_class(cls) || pair_class(cls) || quad_class(cls); }
 
 // blocks per instance for the packing kernels: ~16 entries per thread
 int pack_blocks(int n) { return int(std::min<int64_t>(1024, (int64_t(n) * packed_stride(n) + 4095) / 4096)); }
@@ -972,8 +1016,11 @@ int exchange_class(int n, const int32_t *D, int neighbourhood, int rows)
     if (neighbourhood == DPSO_NB_NODE_SWAP) return kExchangeClasses - 1;
     if (n > 1024 || rows == DPSO_ROWS_BLOCK) return kRowsClass;
     const int mb = n <= 64 ? 0 : n <= 128 ? 1 : n <= 256 ? 2 : n <= 512 ? 3 : 4;
-    if (kHalf && rows == DPSO_ROWS_U16_PAIR && packed_rows(n) && n > 128) return kFirstPairClass + mb - 2;
-    if (kHalf && (rows == DPSO_ROWS_U16 || rows == DPSO_ROWS_U16_PAIR) && packed_rows(n))
+    if (kHalf && rows == DPSO_ROWS_U16_QUAD && packed_rows(n) && n > 256) return kFirstQuadClass + mb - 3;
+    if (kHalf && (rows == DPSO_ROWS_U16_PAIR || rows == DPSO_ROWS_U16_QUAD) && packed_rows(n) && n > 128)
+        return kFirstPairClass + mb - 2;
+    if (kHalf && (rows == DPSO_ROWS_U16 || rows == DPSO_ROWS_U16_PAIR || rows == DPSO_ROWS_U16_QUAD) &&
+        packed_rows(n))
         return kFirstHalfClass + mb;
     const bool vec4 = (n & 3) == 0 && (reinterpret_cast<uintptr_t>(D) & 15) == 0;
     return vec4 ? mb : 5 + mb;
@@ -1007,10 +1054,16 @@ hipError_t launch_batch_2opt(int cls, const Batch &items, int total, int max_ns,
     return launch_class(cls, nullptr, items, total, max_ns, s);
 }
 
-int exchange_merge_group(int cls) { return wave_half_class(cls) ? 1 : pair_class(cls) ? 2 : 0; }
+int exchange_merge_group(int cls)
+{
+    return wave_half_class(cls) ? 1 : pair_class(cls) ? 2 : quad_class(cls) ? 3 : 0;
+}
 
 hipError_t launch_batch_2opt_mixed(int cls, const Batch &items, int total, int max_ns, hipStream_t s)
 {
+    if (quad_class(cls))
+        return cls == kFirstQuadClass ? launch_class(cls, nullptr, items, total, max_ns, s)
+                                      : launch_mixed<16, 4>(items, total, max_ns, s);
     if (pair_class(cls)) {
         switch (cls - kFirstPairClass) {
         case 0: return launch_class(cls, nullptr, items, total, max_ns, s);  // the smallest: one body

@@ -22,7 +22,7 @@ MAX_N = 4096
 MAX_SWARM = 65536
 EE_OFF, EE_ON_STALL, EE_ALWAYS = 0, 1, 2
 NB_TWO_OPT, NB_NODE_SWAP = 0, 1
-ROWS_AUTO, ROWS_U16, ROWS_I32, ROWS_BLOCK, ROWS_U16_PAIR = 0, 1, 2, 3, 4
+ROWS_AUTO, ROWS_U16, ROWS_I32, ROWS_BLOCK, ROWS_U16_PAIR, ROWS_U16_QUAD = 0, 1, 2, 3, 4, 5
 ORDER_DEFAULT, ORDER_INDEX, ORDER_LPT, ORDER_XCD = 0, 1, 2, 3
 MERGE_DEFAULT_PARTICLES = 8192
 

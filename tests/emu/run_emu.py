@@ -366,14 +366,14 @@ def case_merge(emu: Emu) -> bool:
     a multiple of 4 so small n take 16-bit rows too) beside int32, node-swap
     and row-per-workgroup ones, with the 16-bit row classes merged into one
     launch and launched one after another; then the same with two wavefronts
-    per particle above n = 128 (their classes merged apart from the
-    one-wavefront classes of the smaller n)."""
+    per particle above n = 128, and with four above n = 256 (each width's
+    classes merged apart from the others)."""
     ok = True
-    for pair in (False, True):
+    for rows in (0, 4, 5):
         L = emu.L
         L.dpso_tuning_reset()
-        if pair:
-            force_tuning(emu, 256, 4)
+        if rows:
+            force_tuning(emu, 256, rows)
         ok &= _case_merge_once(emu)
     emu.L.dpso_tuning_reset()
     return ok

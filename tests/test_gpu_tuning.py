@@ -11,8 +11,8 @@ from parity import mismatches, note
 
 pytestmark = pytest.mark.gpu
 
-U16, I32, BLOCK, PAIR = 1, 2, 3, 4
-CONFIGS = [(t, r) for t in (64, 128, 256) for r in (U16, I32, BLOCK, PAIR)]
+U16, I32, BLOCK, PAIR, QUAD = 1, 2, 3, 4, 5
+CONFIGS = [(t, r) for t in (64, 128, 256) for r in (U16, I32, BLOCK, PAIR, QUAD)]
 
 
 @pytest.fixture(scope="module")
@@ -34,7 +34,8 @@ def _dev(D):
 def _valid(n, tpb, rows):
     ns = (n + 63) // 64 * 64
     return ns <= 16 * tpb and (rows == BLOCK or (rows == I32 and n <= 1024) or
-                               (rows == U16 and 8 <= n <= 1024) or (rows == PAIR and 128 < n <= 1024))
+                               (rows == U16 and 8 <= n <= 1024) or (rows == PAIR and 128 < n <= 1024) or
+                               (rows == QUAD and 256 < n <= 1024))
 
 
 SIZES = [
@@ -76,7 +77,7 @@ def test_every_configuration_matches_oracle(dp, n, S, gens, kw):
         assert (info["sweeps"], info["moves"], info["reshuffled"]) == (ref.n_sweeps, ref.n_moves, ref.n_reshuffled)
         tried += 1
     dp.tuning_set(n, S, None)
-    assert tried == (2 if n > 1024 else 12 if n > 128 else 9)
+    assert tried == (2 if n > 1024 else 15 if n > 256 else 12 if n > 128 else 9)
 
 
 def _force_everywhere(dp, tpb, rows):
@@ -114,7 +115,7 @@ def test_batch_under_forced_tables_matches_oracle(dp):
         members.append((D, prm))
         refs.append(ref)
     stream = torch.cuda.Stream()
-    for tpb, rows in [(64, U16), (128, I32), (256, BLOCK), (64, BLOCK), (256, PAIR)]:
+    for tpb, rows in [(64, U16), (128, I32), (256, BLOCK), (64, BLOCK), (256, PAIR), (256, QUAD)]:
         _force_everywhere(dp, tpb, rows)
         note(f"batch of {len(members)} under table ({tpb}, {rows})")
         b = dp.Batch([(_dev(D), p) for D, p in members], stream=stream).init()

@@ -120,7 +120,10 @@ def test_tuning_table(dp):
     assert dp.tuning_get(200, 1025) == {"move_threads": 256, "exchange_rows": dp.ROWS_U16}
     assert dp.tuning_get(200, 65536) == {"move_threads": 64, "exchange_rows": dp.ROWS_U16}
     assert dp.tuning_get(384, 65536) == {"move_threads": 64, "exchange_rows": dp.ROWS_U16}
-    assert dp.tuning_get(384, 512) == {"move_threads": 256, "exchange_rows": dp.ROWS_U16_PAIR}
+    assert dp.tuning_get(384, 512) == {"move_threads": 256, "exchange_rows": dp.ROWS_U16_QUAD}
+    assert dp.tuning_get(384, 513)["exchange_rows"] == dp.ROWS_U16_PAIR
+    assert dp.tuning_get(256, 512)["exchange_rows"] == dp.ROWS_I32
+    assert dp.tuning_get(255, 512)["exchange_rows"] == dp.ROWS_U16_PAIR
     assert dp.tuning_get(129, 1024)["exchange_rows"] == dp.ROWS_U16_PAIR
     assert dp.tuning_get(128, 1024)["exchange_rows"] == dp.ROWS_I32
     assert dp.tuning_get(127, 1024)["exchange_rows"] == dp.ROWS_U16
@@ -152,11 +155,11 @@ def test_tuning_table(dp):
         dp.tuning_set(1024, 64, {"move_threads": 64})
         for n, cfg in ((1025, {"move_threads": 64}), (2049, {"move_threads": 128}),
                        (1500, {"exchange_rows": dp.ROWS_U16}), (1500, {"exchange_rows": dp.ROWS_I32}),
-                       (1500, {"exchange_rows": dp.ROWS_U16_PAIR})):
+                       (1500, {"exchange_rows": dp.ROWS_U16_PAIR}), (1500, {"exchange_rows": dp.ROWS_U16_QUAD})):
             with pytest.raises(dp.DpsoError) as e:
                 dp.tuning_set(n, 64, cfg)
             assert e.value.status == dp.E_RANGE, (n, cfg)
-        for cfg in ({"move_threads": 32}, {"move_threads": 512}, {"exchange_rows": 5}, {"exchange_rows": -1}):
+        for cfg in ({"move_threads": 32}, {"move_threads": 512}, {"exchange_rows": 6}, {"exchange_rows": -1}):
             with pytest.raises(dp.DpsoError) as e:
                 dp.tuning_set(100, 64, cfg)
             assert e.value.status == dp.E_INVAL, cfg
@@ -174,6 +177,11 @@ def test_tuning_table(dp):
         assert dp.tuning_get(129, 64)["exchange_rows"] == dp.ROWS_U16_PAIR
         dp.tuning_set(100, 64, {"exchange_rows": dp.ROWS_U16_PAIR})
         assert dp.tuning_get(100, 64)["exchange_rows"] == dp.ROWS_U16
+        # four wavefronts split n > 256; the bucket's smaller n take two
+        dp.tuning_set(400, 64, {"exchange_rows": dp.ROWS_U16_QUAD})
+        assert dp.tuning_get(257, 64)["exchange_rows"] == dp.ROWS_U16_QUAD
+        dp.tuning_set(200, 64, {"exchange_rows": dp.ROWS_U16_QUAD})
+        assert dp.tuning_get(200, 64)["exchange_rows"] == dp.ROWS_U16_PAIR
         # the batch order
         assert dp.batch_order_get() == dp.ORDER_LPT
         for o in (dp.ORDER_INDEX, dp.ORDER_XCD, dp.ORDER_LPT):
