@@ -555,6 +555,36 @@ def test_served_replans_match_oracle(dp, single, chunk):
         assert np.array_equal(rec.tour, o.G), (rec.rid, rec.action)
 
 
+def test_served_large_sites_match_oracle(dp):
+    """Continuous batching over sites of n = 150 ... 700 (swarm 32, so a round
+    of one to three requests takes the four- and two-wavefront rows, merged
+    by group): every served plan equals the oracle replaying the site's
+    actions in request order."""
+    from paper_1706_04399_amd import serve
+    reqs = serve.replan_requests(14, rate=300.0, seed=4, sites=3, n_lo=150, n_hi=700, swarm=32,
+                                 generations=6, change_permille=300, capacity_runs=2)
+    ns = sorted({r.n for r in reqs})
+    forms = {dp.tuning_get(n, 96)["exchange_rows"] for n in ns} | {dp.tuning_get(n, 32)["exchange_rows"] for n in ns}
+    assert dp.ROWS_U16_QUAD in forms, (ns, forms)
+    ex = serve.GpuExecutor(budget_bytes=1 << 34)
+    sched = serve.Scheduler(1 << 34, ex.footprint, max_batch=1024)
+    note(f"served stream of 14 requests over sites n={ns} against the oracle, chunk=4")
+    recs = serve.serve(reqs, ex, sched, chunk=4)
+    assert sorted(r.rid for r in recs) == list(range(14)) and all(r.status == 0 for r in recs)
+    sites = {}
+    for rec in sorted(recs, key=lambda r: r.rid):
+        req = reqs[rec.rid]
+        site = sites.get(req.key)
+        if rec.action != "resume":
+            D = oracle.build_dist(req.scene)
+            site = {"D": D, "st": oracle.new_state(D, req.params)}
+            sites[req.key] = site
+        oracle.run(site["D"], req.params, site["st"], req.generations)
+        o = site["st"]
+        assert (rec.cost, rec.generation) == (o.FG, o.t), (rec.rid, rec.action, req.n)
+        assert np.array_equal(rec.tour, o.G), (rec.rid, rec.action, req.n)
+
+
 def _costs(D, tours):
     """Tour costs recomputed with numpy (independent of both implementations)."""
     t = tours.astype(np.int64)
