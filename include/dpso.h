@@ -405,7 +405,7 @@ dpso_status dpso_import_state(void *d_state, size_t state_bytes, int32_t n, int3
                                 256 < n <= 1024; smaller n take DPSO_ROWS_U16_PAIR) */
 
 typedef struct {
-    int32_t move_threads;  /* 64, 128 or 256 threads per particle (0: default);
+    int32_t move_threads;  /* 64, 128, 256 or 512 threads per particle (0: default);
                               n must be at most 16 * move_threads               */
     int32_t exchange_rows; /* DPSO_ROWS_*; a form that does not serve an n of the
                               bucket falls back: U16_QUAD to U16_PAIR up to

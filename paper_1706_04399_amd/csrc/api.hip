@@ -191,12 +191,12 @@ bool host_velocity_tours(const uint16_t *pairs, int len, int n, uint16_t *from, 
 // prefix tables (per particle, per instance), and for every move class and
 // every edge-exchange class the descriptors of its members with their
 // particle prefix.
-// Move classes: threads per particle 64 / 128 / 256, one launch each; in it
+// Move classes: threads per particle 64 / 128 / 256 / 512, one launch each; in it
 // every member runs at its own positions per thread (the move's mixed batch
 // kernel), not at its class's largest.
-constexpr int kMoveClasses = 3;
+constexpr int kMoveClasses = 4;
 
-int move_class(int tpb) { return tpb == 64 ? 0 : tpb == 128 ? 1 : 2; }
+int move_class(int tpb) { return tpb == 64 ? 0 : tpb == 128 ? 1 : tpb == 512 ? 3 : 2; }
 
 int move_class_threads(int mc) { return 64 << mc; }
 
@@ -837,7 +837,7 @@ dpso_status dpso_autotune(const int32_t *d_dist, int32_t n, const dpso_params *p
     };
     // phase 1: threads per particle in the move, the exchange at its default
     const int ns = L.ns;
-    for (int tpb : {64, 128, 256}) {
+    for (int tpb : {64, 128, 256, 512}) {
         if (!dpso::move_threads_ok(tpb, ns)) continue;
         st = trial(dpso::Tune{tpb, dflt.exchange_rows});
         if (st) return finish(st);

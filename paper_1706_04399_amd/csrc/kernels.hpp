@@ -11,7 +11,7 @@ namespace dpso {
 // swarm.hip: one instance (descriptor by value)
 hipError_t launch_init(const Inst &I, hipStream_t s);
 hipError_t launch_check(const Inst &I, hipStream_t s);
-// the move at tpb (64, 128 or 256) threads per particle; move_threads_ok
+// the move at tpb (64, 128, 256 or 512) threads per particle; move_threads_ok
 // tells whether tpb serves row stride ns (at most 16 positions per thread)
 bool move_threads_ok(int tpb, int ns);
 hipError_t launch_move(const Inst &I, int tpb, hipStream_t s);

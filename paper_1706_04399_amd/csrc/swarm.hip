@@ -249,8 +249,8 @@ __device__ __forceinline__ void init_body(const Inst &I, int p)
 // the move); its transposition list is the canonical to - from.
 namespace {
 
-// Threads per particle of the move (TPB, a template argument): 64, 128 or
-// 256; every loop takes EPT = ceil(ns / TPB) positions per thread.
+// Threads per particle of the move (TPB, a template argument): 64, 128, 256
+// or 512; every loop takes EPT = ceil(ns / TPB) positions per thread.
 constexpr int kMaxMoveThreads = 256;
 constexpr uint16_t kEmit = 1u << 14;   // in rho[p]: p is not the largest of its cycle
 constexpr uint16_t kFixed = 1u << 15;  // in rho[p]: p is among the first k of those
@@ -263,7 +263,7 @@ constexpr uint16_t kLabel = 0x0fff;    // labels and positions (n <= 4096)
 struct MoveLds {
     uint16_t *x, *posx, *from, *posf, *to, *rho, *cur, *z;
     uint32_t *e0, *e1;
-    int *wsum;   // 4 per-wave sums
+    int *wsum;   // 8 per-wave sums
     int *vote;   // 3 rotating flags of vote_any
     int round;   // vote count so far (identical in every thread)
 };
@@ -297,7 +297,7 @@ __device__ MoveLds carve_move_lds(unsigned char *base, int nl)
     L.e0 = reinterpret_cast<uint32_t *>(u);  // 12 nl bytes in: 16-byte aligned
     L.e1 = L.e0 + nl;
     L.wsum = reinterpret_cast<int *>(L.e1 + nl);
-    L.vote = L.wsum + 4;
+    L.vote = L.wsum + 8;
     L.round = 0;
     return L;
 }
@@ -997,7 +997,7 @@ hipError_t launch_move_tpb(const Target &t, size_t lds, hipStream_t s)
 
 bool move_threads_ok(int tpb, int ns)
 {
-    return (tpb == 64 || tpb == 128 || tpb == 256) && ns <= 16 * tpb;
+    return (tpb == 64 || tpb == 128 || tpb == 256 || tpb == 512) && ns <= 16 * tpb;
 }
 
 hipError_t launch_move_t(const Target &t, int tpb, hipStream_t s)
@@ -1007,6 +1007,7 @@ hipError_t launch_move_t(const Target &t, int tpb, hipStream_t s)
     if (!move_threads_ok(tpb, t.max_ns)) return hipErrorInvalidConfiguration;
     if (tpb == 64) return launch_move_tpb<64>(t, lds, s);
     if (tpb == 128) return launch_move_tpb<128>(t, lds, s);
+    if (tpb == 512) return launch_move_tpb<512>(t, lds, s);
     return launch_move_tpb<256>(t, lds, s);
 }
 

@@ -161,8 +161,9 @@ dpso_status dpso_tuning_set(int32_t n, int32_t particles, const dpso_tuning *t)
     const int bn = dpso::tune_bucket_n(n), bp = dpso::tune_bucket_p(particles);
     dpso::Tune e{0, 0};
     if (t) {
-        if (t->move_threads != 0 && t->move_threads != 64 && t->move_threads != 128 && t->move_threads != 256)
-            return fail(DPSO_E_INVAL, "move_threads = %d is not 0, 64, 128 or 256", t->move_threads);
+        if (t->move_threads != 0 && t->move_threads != 64 && t->move_threads != 128 && t->move_threads != 256 &&
+            t->move_threads != 512)
+            return fail(DPSO_E_INVAL, "move_threads = %d is not 0, 64, 128, 256 or 512", t->move_threads);
         if (t->exchange_rows < DPSO_ROWS_AUTO || t->exchange_rows > DPSO_ROWS_U16_QUAD)
             return fail(DPSO_E_INVAL, "exchange_rows = %d is not a DPSO_ROWS_* value", t->exchange_rows);
         const int top = dpso::bucket_max_n(bn), ns = (top + 63) & ~63;

@@ -8,7 +8,7 @@
 namespace dpso {
 
 struct Tune {
-    int move_threads;   // 64, 128 or 256 threads per particle in the move
+    int move_threads;   // 64, 128, 256 or 512 threads per particle in the move
     int exchange_rows;  // DPSO_ROWS_U16, _I32 or _BLOCK (resolved, never AUTO)
 };
 

@@ -367,13 +367,14 @@ def case_merge(emu: Emu) -> bool:
     and row-per-workgroup ones, with the 16-bit row classes merged into one
     launch and launched one after another; then the same with two wavefronts
     per particle above n = 128, and with four above n = 256 (each width's
-    classes merged apart from the others)."""
+    classes merged apart from the others), the last with the move at 512
+    threads per particle."""
     ok = True
-    for rows in (0, 4, 5):
+    for tpb, rows in ((0, 0), (256, 4), (256, 5), (512, 5)):
         L = emu.L
         L.dpso_tuning_reset()
         if rows:
-            force_tuning(emu, 256, rows)
+            force_tuning(emu, tpb, rows)
         ok &= _case_merge_once(emu)
     emu.L.dpso_tuning_reset()
     return ok

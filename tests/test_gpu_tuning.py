@@ -12,7 +12,7 @@ from parity import mismatches, note
 pytestmark = pytest.mark.gpu
 
 U16, I32, BLOCK, PAIR, QUAD = 1, 2, 3, 4, 5
-CONFIGS = [(t, r) for t in (64, 128, 256) for r in (U16, I32, BLOCK, PAIR, QUAD)]
+CONFIGS = [(t, r) for t in (64, 128, 256, 512) for r in (U16, I32, BLOCK, PAIR, QUAD)]
 
 
 @pytest.fixture(scope="module")
@@ -77,7 +77,7 @@ def test_every_configuration_matches_oracle(dp, n, S, gens, kw):
         assert (info["sweeps"], info["moves"], info["reshuffled"]) == (ref.n_sweeps, ref.n_moves, ref.n_reshuffled)
         tried += 1
     dp.tuning_set(n, S, None)
-    assert tried == (2 if n > 1024 else 15 if n > 256 else 12 if n > 128 else 9)
+    assert tried == (3 if n > 1024 else 20 if n > 256 else 16 if n > 128 else 12)
 
 
 def _force_everywhere(dp, tpb, rows):
@@ -143,7 +143,7 @@ def test_autotune_leaves_swarm_and_records_pick(dp, n, S, kw):
     assert len({r["digest"] for r in res}) == 1
     # 3 (or 2) move widths, then the row forms other than the default (int32
     # rows are not a separate candidate for an n off 16 bytes)
-    assert len(res) == {200: 6, 30: 4, 1500: 2}[n]
+    assert len(res) == {200: 7, 30: 5, 1500: 3}[n]
     assert all(r["ms"] > 0 for r in res)
     after = dp.export_state(state, n, S)
     for k in ("X", "P", "V", "vlen", "F", "FP", "G", "trace"):

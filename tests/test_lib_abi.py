@@ -159,7 +159,7 @@ def test_tuning_table(dp):
             with pytest.raises(dp.DpsoError) as e:
                 dp.tuning_set(n, 64, cfg)
             assert e.value.status == dp.E_RANGE, (n, cfg)
-        for cfg in ({"move_threads": 32}, {"move_threads": 512}, {"exchange_rows": 6}, {"exchange_rows": -1}):
+        for cfg in ({"move_threads": 32}, {"move_threads": 1024}, {"exchange_rows": 6}, {"exchange_rows": -1}):
             with pytest.raises(dp.DpsoError) as e:
                 dp.tuning_set(100, 64, cfg)
             assert e.value.status == dp.E_INVAL, cfg
